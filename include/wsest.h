@@ -1,0 +1,225 @@
+/*
+ * wsest — analytic GPU data-volume and performance estimator, MI355X (gfx950).
+ *
+ * Implements the data-parallel hot path of the method of Ernst, Holzer,
+ * Hager, Knorr and Wellein, "Analytical Performance Estimation during Code
+ * Generation on Modern GPUs": for every configuration of a configuration
+ * space, the per-thread address expressions of a kernel are evaluated for
+ * every thread of a warp, of a representative thread block, of a wave of
+ * co-resident blocks and of the layer-condition thread sets; the distinct
+ * 32 B sectors and 128 B lines they touch are counted; the counts become L1
+ * cycles, L2->L1 and DRAM volumes through the capacity-miss model, then a
+ * four-limiter performance estimate and a ranking.
+ *
+ * Every step runs in HIP kernels on the GPU; the host only validates,
+ * plans memory and launches.
+ *
+ * Conventions
+ *   - Every call returns a wse_status: WSE_OK (0) or a negative code.  No C++
+ *     exception crosses this interface.  wse_last_error() returns the text
+ *     of the last failure on the calling thread.
+ *   - Inputs are caller-owned and copied before the call returns.
+ *   - Output buffers are caller-owned and may be host or device (HIP)
+ *     memory; they must stay valid until the call returns (wse_estimate)
+ *     or the ticket completes (wse_submit).
+ *   - The library owns one device arena per context, sized at creation;
+ *     per-configuration hash tables are carved from it.
+ *   - Streams are passed as void* (a hipStream_t); NULL = the default stream.
+ *   - A problem with one configuration does not fail the call: it is
+ *     reported in that configuration's wse_result.status.
+ */
+#ifndef WSEST_H
+#define WSEST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wse_status;
+#define WSE_OK 0
+#define WSE_EINVAL (-1)    /* invalid argument or configuration */
+#define WSE_ENOMEM (-2)    /* arena or host memory exhausted */
+#define WSE_ERANGE (-3)    /* address or key outside the representable range */
+#define WSE_EDEVICE (-4)   /* HIP runtime error */
+#define WSE_EBUSY (-5)     /* server queue full */
+#define WSE_ENOTREADY (-6) /* request not finished yet */
+
+typedef struct wse_ctx wse_ctx;
+typedef struct wse_server wse_server;
+
+/* Create a context on HIP device `device` with a device arena of
+ * `arena_bytes` (0 = a default of 4 GiB).  *out receives the context. */
+wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out);
+/* Destroy a context; stops its server if one is running. */
+void wse_ctx_destroy(wse_ctx* ctx);
+/* Static text of a status code. */
+const char* wse_status_str(wse_status s);
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* wse_last_error(const wse_ctx* ctx);
+
+/* ---------------------------------------------------------------- kernels */
+
+/* A field (array) accessed by the kernel.  The base pointer is unknown when
+ * code is generated, so it is replaced by the field's alignment (Sec. 4.3);
+ * fields never alias. */
+typedef struct {
+    int32_t elem_bytes;   /* element size in bytes, > 0 */
+    int32_t pad;
+    int64_t align_bytes;  /* byte address of element 0 */
+} wse_field;
+
+/* Raw affine address expression (Sec. 1.2): the element index of one load
+ * or store is c0 + sum_d ct[d]*tid_d + cb[d]*bid_d + cg[d]*gid_d with
+ * gid = bid*blockDim + tid; the byte address is align + elem_bytes*index. */
+typedef struct {
+    int32_t field, is_store;
+    int64_t c0;
+    int64_t ct[3], cb[3], cg[3];
+} wse_expr;
+
+/* Lattice access: the field value at the updated point plus off[] (a
+ * relative field access, Sec. 1.2).  A lattice kernel on a domain D uses
+ * x-fastest arrays of (D + 2*ghost) elements per dimension whose interior
+ * starts at (ghost, ghost, ghost).  With thread folding (Sec. 5.2) a thread
+ * of global id (gx, gy, gz) updates the points (gx, fy*gy + j, fz*gz + k),
+ * j < fy, k < fz; accesses of one thread naming the same field, kind and
+ * point are one register value and issue one instruction. */
+typedef struct {
+    int32_t field, is_store;
+    int32_t off[3];
+    int32_t pad;
+} wse_access;
+
+#define WSE_KERNEL_LATTICE 0
+#define WSE_KERNEL_AFFINE 1
+
+typedef struct {
+    int32_t kind;             /* WSE_KERNEL_LATTICE or WSE_KERNEL_AFFINE */
+    int32_t n_fields;         /* 1 .. 65535 */
+    int32_t n_items;          /* accesses or expressions, 1 .. 65535 */
+    int32_t ghost;            /* lattice: ghost layers per side, >= 0 */
+    const wse_field* fields;  /* [n_fields] */
+    const void* items;        /* wse_access[n_items] or wse_expr[n_items] */
+    double flops_per_lup;     /* floating-point ops per lattice update; 0 = FP limiter off */
+} wse_kernel_desc;
+
+/* Register a kernel; its tables are copied to the device and stay resident
+ * for the life of the context.  *kernel_id receives its handle. */
+wse_status wse_kernel_register(wse_ctx* ctx, const wse_kernel_desc* desc, int32_t* kernel_id);
+
+/* ---------------------------------------------------------------- hardware */
+
+/* Hit-rate estimate R(O) = a * exp(-b * exp(c * O)) of redundant volume at
+ * oversubscription O = V_alloc / V_cache (Sec. 4.5; the sign is chosen so
+ * that R falls from a toward 0 as O grows; 0 <= a <= 1, b >= 0, c >= 0). */
+typedef struct {
+    double a, b, c;
+} wse_fit;
+
+/* Modelled GPU (Sec. 3, Table 1 lists the paper's two). */
+typedef struct {
+    int32_t line_bytes;          /* allocation granularity (128), power of two */
+    int32_t sector_bytes;        /* transfer granularity (32), power of two, <= line */
+    int32_t warp_size;           /* 1 .. 64, power of two */
+    int32_t l1_group_lanes;      /* lanes served per L1 cycle (16), power of two, divides warp */
+    int32_t l1_banks;            /* L1 banks (16), power of two, <= 64 */
+    int32_t l1_bank_bytes;       /* bank width (8), power of two */
+    int32_t l1_pair_bytes;       /* addresses this far apart never share a cycle (1024) */
+    int32_t n_cu;                /* compute units */
+    int32_t blocks_per_cu;       /* resident blocks per CU */
+    int32_t max_threads_per_cu;  /* resident threads per CU */
+    int64_t l1_bytes, l2_bytes;  /* cache capacities */
+    double clock_hz, bw_l2, bw_dram, flops_peak;   /* flops_peak 0 = FP limiter off */
+    wse_fit fit_l1, fit_l2_y, fit_l2_z, fit_l2_store;   /* the x layer set uses fit_l2_y */
+} wse_hw;
+
+/* Register a hardware description; kept resident on the device. */
+wse_status wse_hw_register(wse_ctx* ctx, const wse_hw* hw, int32_t* hw_id);
+
+/* ----------------------------------------------------------------- spaces */
+
+/* A configuration space (Sec. 5.1).  Block shapes are (2^a, 2^b, 2^c) with
+ * bit a of bx_exp_mask, bit b of by_exp_mask and bit c of bz_exp_mask set
+ * and a thread count in [min_threads, max_threads], ordered by (a, b, c)
+ * lexicographically.  Lattice spaces add folding factors fy = 2^i (bit i of
+ * fy_exp_mask), fz likewise, element sizes (elem_mask bit0 = 4 B, bit1 =
+ * 8 B; 0 = each field's own size) and domains; affine spaces add grids
+ * (blocks per dimension).  The canonical index of a configuration is mixed
+ * radix over (domain|grid, elem, fz, fy, shape), slowest first; results and
+ * rank ties follow it.  With n_explicit > 0 only the listed canonical
+ * indices are estimated, in the given order. */
+typedef struct {
+    int32_t kernel_id, hw_id;
+    uint32_t bx_exp_mask, by_exp_mask, bz_exp_mask;
+    int32_t min_threads, max_threads;
+    uint32_t fy_exp_mask, fz_exp_mask;   /* lattice; ignored for affine spaces */
+    uint32_t elem_mask;                  /* lattice; ignored for affine spaces */
+    int32_t n_outer;                     /* number of domains or grids */
+    const int32_t* outer;                /* 3 int32 per domain (lattice) or grid (affine) */
+    int64_t n_explicit;
+    const int64_t* explicit_idx;
+} wse_space;
+
+/* Number of configurations the space describes (n_explicit if given). */
+wse_status wse_space_size(wse_ctx* ctx, const wse_space* space, int64_t* n_configs);
+
+/* ----------------------------------------------------------------- results */
+
+/* Per-configuration result.  Counts are exact; volumes are in sectors
+ * (multiply by sector_bytes for bytes).  Suffix B = representative (centre)
+ * thread block, W = middle wave of co-resident blocks, L = layer sets.
+ * s_layer[d] = first block of the layer set of dimension d, -1 if empty. */
+typedef struct {
+    int32_t status, limiter;     /* limiter 0 L1, 1 L2, 2 DRAM, 3 FP; -1 on error */
+    int32_t shape[3], fold[3], domain[3], elem;   /* domain = grid for affine */
+    int64_t index, n_expr;       /* canonical index; instructions per thread */
+    int64_t lups_B, warps_B, l1_cycles_B, up_ld_B, up_st_B, comp_ld_B, lines_ld_B;
+    int64_t blocks_W, lups_W, fpld_W, comp_st_W, up_st_W, lines_W;
+    int64_t s_layer[3], lines_L[3], shell[3];
+    double O_l1, R_l1, v_l2l1_ld, O_W, R_st, O_L[3], R_L[3], v_dram_ld, v_dram_st;
+    double bpl_l2, bpl_dram, p_l1, p_l2, p_dram, p_fp, perf;   /* bytes/LUP, LUP/s */
+} wse_result;
+
+#define WSE_PLAIN 0    /* one launch sequence per configuration, host sync between */
+#define WSE_BATCHED 1  /* all configurations of all spaces in stage-wide launches */
+
+/* Estimate every configuration of n_spaces spaces.  out[] receives the
+ * results of space 0, then space 1, ...; rank_out[] (optional) the 0-based
+ * rank of each configuration within its space (perf descending, canonical
+ * index ascending).  out_capacity = entries available in out/rank_out.
+ * Returns after the results are written (the stream is synchronised). */
+wse_status wse_estimate(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces,
+                        wse_result* out, int32_t* rank_out, int64_t out_capacity,
+                        int32_t mode, void* stream);
+
+/* Evaluate the hit-rate estimate R(O) of `fit` on the device for n values
+ * O[i] (Sec. 4.5), with the same arithmetic the model uses.  O and R may be
+ * host or device pointers of n doubles. */
+wse_status wse_rhat(wse_ctx* ctx, const wse_fit* fit, const double* O, double* R, int64_t n,
+                    void* stream);
+
+/* Device time in milliseconds of each stage of the last wse_estimate call
+ * on this context, measured with HIP events on the call's stream: [0]
+ * expand+decode (including the host read-back of the plan), [1] evaluation
+ * kernels, [2] counting kernels, [3] model+rank.  `n` entries (<= 8) are
+ * copied. */
+wse_status wse_last_timings(const wse_ctx* ctx, double* ms, int32_t n);
+
+/* Work statistics of the last wse_estimate call on this context (n <= 8
+ * entries): [0] (thread, instruction) address evaluations performed over all
+ * thread sets, [1] hash-table bytes used, [2] evaluation-kernel launches,
+ * [3] arena rounds, [4] configurations evaluated. */
+wse_status wse_last_stats(wse_ctx* ctx, int64_t* stats, int32_t n);
+
+/* Address evaluations the last wse_estimate call performed for each of its
+ * configurations (same order as its results); `evals` is a host array of
+ * n entries, n <= the call's configuration count. */
+wse_status wse_last_evals(wse_ctx* ctx, int64_t* evals, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

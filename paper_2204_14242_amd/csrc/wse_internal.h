@@ -1,0 +1,163 @@
+// Internal records shared by the host scheduler (wse_api.cpp) and the HIP
+// kernels (wse_kernels.hip).  Not part of the public interface.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace wse {
+
+// hash tables of one configuration
+enum { T_BSEC = 0, T_BLINE = 1, T_WSEC = 2, T_WLINE = 3, T_LLINE = 4, N_TABLES = 5 };
+// thread sets evaluated for one configuration
+enum { PASS_B = 0, PASS_W = 1, PASS_L = 2 };
+// insert semantics of a table entry's payload bits
+enum { MODE_SET = 0, MODE_OR = 1, MODE_MAX = 2 };
+
+constexpr int kLanes = 64;          // gfx950 wavefront
+constexpr int kWavesPerGroup = 4;   // evaluation workgroup = 4 independent waves
+
+// Open-addressing table of 8-byte entries ((key + 1) << pb) | payload; 0 = empty.
+// key = field * span + (unit - umin) for unit = floor(address / granularity).
+struct TableDesc {
+    int64_t umin;
+    int64_t span;
+    int64_t off;       // byte offset of the slots in the arena (host-assigned)
+    int64_t tag_off;   // byte offset of an int32 tag per slot (W sector table), -1 if none
+    int32_t log2cap;   // capacity = 2^log2cap slots; 0 = unused
+    int32_t pb;        // payload bits
+};
+
+// resident kernel
+struct KernelDev {
+    int32_t kind, n_fields, n_items, ghost;
+    const int32_t* elem;   // [n_fields]
+    const int64_t* align;  // [n_fields]
+    const void* items;     // lattice: AccessL[n_items]; affine: ExprA[n_items]
+    double flops_per_lup;
+    int32_t uniform_elem;  // all fields share one element size (0 if not)
+    int32_t pad;
+};
+
+struct AccessL {
+    int32_t f, st, o[3], pad;
+};
+
+struct ExprA {
+    int32_t f, st;
+    int64_t c0, ct[3], cb[3], cg[3];
+};
+
+// expanded lattice instruction: field, kind and offset of the updated point
+struct ExprL {
+    int32_t f, st, v[3], pad;
+};
+
+struct HwDev {
+    int32_t line_bytes, sector_bytes, warp_size, l1_group_lanes, l1_banks, l1_bank_bytes;
+    int32_t l1_pair_bytes, n_cu, blocks_per_cu, max_threads_per_cu;
+    int32_t log2_line, log2_sector, log2_bank, log2_warp, log2_group, pair_words;
+    int64_t l1_bytes, l2_bytes;
+    double clock_hz, bw_l2, bw_dram, flops_peak;
+    double fit[4][3];
+};
+
+struct Expansion {
+    const ExprL* ex;
+    int32_t E;
+    int32_t n_ld;
+};
+
+struct SpaceDev {
+    int32_t kernel_id, hw_id, kind;
+    int32_t n_shapes, n_fy, n_fz, n_elem, n_outer;
+    const int32_t* shapes;      // 3 log2 extents per shape, canonical order
+    int32_t fy[8], fz[8], elem[2];
+    const int32_t* outer;       // 3 per domain/grid
+    const int64_t* explicit_idx;  // nullptr = all
+    int64_t n_configs;
+    int64_t first;              // index of the space's first configuration in the call
+    int32_t exp_id[8][8];       // expansion per (fy index, fz index); lattice only
+};
+
+struct Cfg {
+    int32_t status, kind;
+    int32_t space, kernel_id, hw_id, expansion_id;
+    int64_t index;              // canonical index in the space
+    int32_t b[3], lb[3], fold[3], outer[3];
+    int32_t elem;               // lattice element override (0 = fields' own)
+    int32_t E, n_ld, segs_per_block;
+    int32_t tag_bits, uniform_elem;
+    int64_t T[3], nb[3];
+    int64_t P, occ, N, nbt, w0, w1, kB, smin;
+    int64_t s[3];
+    int32_t order[3], n_order;  // non-empty layer sets by recency
+    int64_t sy, sz, g;
+    int64_t evals[3];           // thread x instruction evaluations per pass (upper bound)
+    TableDesc tab[N_TABLES];
+    int64_t table_bytes;        // arena bytes this configuration needs
+};
+
+// per-configuration accumulators (int64 atomics)
+struct Counters {
+    unsigned long long lanes_B, warps_B, l1_cycles_B, up_ld_B, up_st_B, comp_ld_B, lines_ld_B;
+    unsigned long long lanes_W, fpld_W, comp_st_W, up_st_W, lines_W;
+    unsigned long long lines_L[3], shell[3];
+    unsigned long long err;     // bit0 key out of range, bit1 table overflow
+    unsigned long long lanes_L;
+    unsigned long long pad[2];
+};
+
+// a contiguous range of work of one configuration, split into equal items
+struct WorkEntry {
+    int32_t cfg;
+    int32_t what;       // pass (evaluation) or table (counting)
+    int64_t n_units;    // segments of 64 threads, or table slots
+    int64_t per_item;
+    int64_t item_start;
+};
+
+struct Result {  // identical layout to wse_result
+    int32_t status, limiter;
+    int32_t shape[3], fold[3], domain[3], elem;
+    int64_t index, n_expr;
+    int64_t lups_B, warps_B, l1_cycles_B, up_ld_B, up_st_B, comp_ld_B, lines_ld_B;
+    int64_t blocks_W, lups_W, fpld_W, comp_st_W, up_st_W, lines_W;
+    int64_t s_layer[3], lines_L[3], shell[3];
+    double O_l1, R_l1, v_l2l1_ld, O_W, R_st, O_L[3], R_L[3], v_dram_ld, v_dram_st;
+    double bpl_l2, bpl_dram, p_l1, p_l2, p_dram, p_fp, perf;
+};
+
+struct DevTables {
+    const KernelDev* kernels;
+    const HwDev* hws;
+    const Expansion* expansions;
+    const SpaceDev* spaces;
+    int32_t n_spaces;
+};
+
+// ---- launchers (wse_kernels.hip) ----
+struct ExpandJob {
+    int32_t kernel_id, fy, fz, pad;
+    ExprL* out;      // capacity n_items*fy*fz
+    int32_t* scratch_keep;
+    Expansion* slot; // where E is written
+};
+
+hipError_t launch_expand(const ExpandJob* jobs_dev, int n_jobs, DevTables t, hipStream_t s);
+hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int64_t lds_slots, hipStream_t s);
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
+hipError_t launch_eval(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr, const WorkEntry* work,
+                       int n_work, int64_t n_items, char* arena, DevTables t, int lds_slots,
+                       int64_t max_groups, hipStream_t s);
+hipError_t launch_count(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr, const WorkEntry* work,
+                        int n_work, int64_t n_items, const char* arena, int64_t max_groups,
+                        hipStream_t s);
+hipError_t launch_reduce(const Cfg* cfgs, const Counters* ctr, int64_t n, DevTables t,
+                         Result* out, hipStream_t s);
+hipError_t launch_rhat(const double* fit, const double* O, double* R, int64_t n, hipStream_t s);
+hipError_t launch_rank(const Result* res, const int64_t* space_first, const int32_t* cfg_space,
+                       int64_t n, int32_t* rank, hipStream_t s);
+
+}  // namespace wse

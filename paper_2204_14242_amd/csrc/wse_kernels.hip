@@ -1,0 +1,1128 @@
+// HIP kernels of the estimator's hot path for gfx950 (wave64).
+//
+//   k_expand_*   folding expansion of lattice accesses into per-thread
+//                instructions (register reuse of equal points, Sec. 5.2/5.4)
+//   k_decode     configuration-space enumeration: canonical index -> block
+//                shape, folding, domain, element size; derived grid, wave,
+//                representative block, layer-set starts, key ranges and
+//                hash-table sizes (Sec. 4.4, 5.1)
+//   k_eval       address evaluation of every (thread, instruction) of the
+//                representative block, the wave and the layer sets; per-warp
+//                distinct sectors and L1 bank cycles by wavefront ballots;
+//                distinct sectors/lines through per-wave LDS hash sets
+//                flushed into per-configuration HBM hash sets (Sec. 4.2-4.4)
+//   k_count      cardinalities of the HBM sets, recency shells and layer
+//                line counts (Sec. 4.4.2)
+//   k_reduce     capacity-miss model and four-limiter performance (Sec. 4.5, 2)
+//   k_rank       rank within each space (perf descending, index ascending)
+//
+// All model arithmetic is IEEE binary64 in a fixed order; the library is
+// built with -ffp-contract=off so that no multiply-add is fused implicitly.
+#include "wse_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace wse {
+
+// ------------------------------------------------------------------ helpers
+
+// 64-bit mixing function (MurmurHash3 finaliser)
+__device__ __forceinline__ uint64_t mix64(uint64_t k)
+{
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kLanes - 1)); }
+
+__device__ __forceinline__ int64_t readlane64(int64_t v, int l)
+{
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int64_t shfl64(int64_t v, int src)
+{
+    uint32_t lo = (uint32_t)__shfl((int)(uint32_t)(uint64_t)v, src);
+    uint32_t hi = (uint32_t)__shfl((int)(uint32_t)((uint64_t)v >> 32), src);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int64_t shfl_xor64(int64_t v, int m)
+{
+    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)(uint64_t)v, m);
+    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)((uint64_t)v >> 32), m);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int bits_for(uint64_t x)  // bits needed to hold x
+{
+    return x == 0 ? 0 : 64 - __clzll((long long)x);
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v)
+{
+    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor64(v, m);
+    return v;
+}
+
+__device__ __forceinline__ void wave_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// --------------------------------------------------------- hash-set inserts
+
+// Insert into an open-addressing set (linear probing).  Entry layout
+// ((key + 1) << pb) | payload.  Returns 1 if a new key was placed, 0 if the
+// key was present (payload merged by `mode`), -1 if the table is full.
+template <bool LDS>
+__device__ __forceinline__ int set_insert(unsigned long long* slots, uint64_t mask, uint64_t entry,
+                                          int pb, int mode)
+{
+    uint64_t key1 = entry >> pb;
+    uint64_t pos = mix64(key1) & mask;
+    for (uint64_t probe = 0; probe <= mask; probe++) {
+        unsigned long long old = atomicCAS(&slots[pos], 0ull, (unsigned long long)entry);
+        if (old == 0) return 1;
+        if ((old >> pb) == key1) {
+            if (mode == MODE_MAX) {
+                if (entry > old) atomicMax(&slots[pos], (unsigned long long)entry);
+            } else if (mode == MODE_OR) {
+                if ((old | entry) != old) atomicOr(&slots[pos], (unsigned long long)entry);
+            }
+            return 0;
+        }
+        pos = (pos + 1) & mask;
+    }
+    return -1;
+}
+
+// position of key1 in a global table, -1 if absent
+__device__ __forceinline__ int64_t set_find(const unsigned long long* slots, uint64_t mask,
+                                            uint64_t key1, int pb)
+{
+    uint64_t pos = mix64(key1) & mask;
+    for (uint64_t probe = 0; probe <= mask; probe++) {
+        unsigned long long e = __hip_atomic_load(&slots[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (e == 0) return -1;
+        if ((e >> pb) == key1) return (int64_t)pos;
+        pos = (pos + 1) & mask;
+    }
+    return -1;
+}
+
+// ------------------------------------------------------------ expansion
+
+// keep[c] = 1 iff candidate c (access a, fold offsets j, q) names a point no
+// earlier candidate of the same field and kind names
+__global__ void k_expand_mark(const ExpandJob* jobs, DevTables t)
+{
+    const ExpandJob& J = jobs[blockIdx.y];
+    const KernelDev& K = t.kernels[J.kernel_id];
+    const AccessL* acc = (const AccessL*)K.items;
+    int ff = J.fy * J.fz;
+    int n = K.n_items * ff;
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    int a = c / ff, r = c % ff;
+    int f = acc[a].f, st = acc[a].st;
+    int vx = acc[a].o[0], vy = acc[a].o[1] + r / J.fz, vz = acc[a].o[2] + r % J.fz;
+    int keep = 1;
+    for (int d = 0; d < c && keep; d++) {
+        int a2 = d / ff, r2 = d % ff;
+        if (acc[a2].f == f && acc[a2].st == st && acc[a2].o[0] == vx &&
+            acc[a2].o[1] + r2 / J.fz == vy && acc[a2].o[2] + r2 % J.fz == vz)
+            keep = 0;
+    }
+    J.scratch_keep[c] = keep;
+}
+
+// stable compaction of the kept candidates; one workgroup per job
+__global__ void k_expand_compact(const ExpandJob* jobs, DevTables t)
+{
+    const ExpandJob& J = jobs[blockIdx.x];
+    const KernelDev& K = t.kernels[J.kernel_id];
+    const AccessL* acc = (const AccessL*)K.items;
+    int ff = J.fy * J.fz;
+    int n = K.n_items * ff;
+    __shared__ int scan[1024];
+    __shared__ int base_s;
+    if (threadIdx.x == 0) base_s = 0;
+    __syncthreads();
+    int n_ld = 0;
+    for (int c0 = 0; c0 < n; c0 += 1024) {
+        int c = c0 + (int)threadIdx.x;
+        int k = c < n ? J.scratch_keep[c] : 0;
+        scan[threadIdx.x] = k;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
+            __syncthreads();
+            scan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        int base = base_s;
+        if (k) {
+            int a = c / ff, r = c % ff;
+            ExprL e;
+            e.f = acc[a].f;
+            e.st = acc[a].st;
+            e.v[0] = acc[a].o[0];
+            e.v[1] = acc[a].o[1] + r / J.fz;
+            e.v[2] = acc[a].o[2] + r % J.fz;
+            e.pad = 0;
+            J.out[base + scan[threadIdx.x] - 1] = e;
+            if (!e.st) n_ld++;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) base_s = base + scan[1023];
+        __syncthreads();
+    }
+    // loads among the kept instructions
+    for (int off = 32; off >= 1; off >>= 1) n_ld += __shfl_xor(n_ld, off);
+    __shared__ int nld_s;
+    if (threadIdx.x == 0) nld_s = 0;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) atomicAdd(&nld_s, n_ld);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        J.slot->ex = J.out;
+        J.slot->E = base_s;
+        J.slot->n_ld = nld_s;
+    }
+}
+
+hipError_t launch_expand(const ExpandJob* jobs_dev, int n_jobs, DevTables t, hipStream_t s)
+{
+    if (n_jobs == 0) return hipSuccess;
+    // candidates per job are at most 65536 (checked by the host)
+    dim3 g1(65536 / 256, n_jobs);
+    hipLaunchKernelGGL(k_expand_mark, g1, dim3(256), 0, s, jobs_dev, t);
+    hipLaunchKernelGGL(k_expand_compact, dim3(n_jobs), dim3(1024), 0, s, jobs_dev, t);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- decode
+
+struct Range {
+    int64_t lo, hi;
+};
+
+// smallest and largest unit (address >> log2u) any valid thread of the
+// blocks [klo, khi) reaches with any instruction
+__device__ void unit_range(const Cfg& c, const KernelDev& K, const Expansion* X, int64_t klo,
+                           int64_t khi, int log2u, int64_t* umin, int64_t* umax, int* bad)
+{
+    int64_t nxy = c.nb[0] * c.nb[1];
+    int64_t blo[3], bhi[3];
+    int64_t zlo = klo / nxy, zhi = (khi - 1) / nxy;
+    blo[2] = zlo;
+    bhi[2] = zhi;
+    if (zlo == zhi) {
+        int64_t ylo = (klo / c.nb[0]) % c.nb[1], yhi = ((khi - 1) / c.nb[0]) % c.nb[1];
+        blo[1] = ylo;
+        bhi[1] = yhi;
+        if (ylo == yhi) {
+            blo[0] = klo % c.nb[0];
+            bhi[0] = (khi - 1) % c.nb[0];
+        } else {
+            blo[0] = 0;
+            bhi[0] = c.nb[0] - 1;
+        }
+    } else {
+        blo[1] = 0;
+        bhi[1] = c.nb[1] - 1;
+        blo[0] = 0;
+        bhi[0] = c.nb[0] - 1;
+    }
+    __int128 lo = 0, hi = 0;
+    bool first = true;
+    const __int128 LIM = (__int128)1 << 62;
+    if (c.kind == 0) {
+        int64_t glo[3], ghi[3];
+        for (int d = 0; d < 3; d++) {
+            glo[d] = blo[d] * c.b[d];
+            int64_t h = (bhi[d] + 1) * c.b[d];
+            ghi[d] = (h < c.T[d] ? h : c.T[d]) - 1;
+        }
+        __int128 blo_ = (__int128)(glo[0] + c.g) + (__int128)c.sy * (c.fold[1] * glo[1] + c.g) +
+                        (__int128)c.sz * (c.fold[2] * glo[2] + c.g);
+        __int128 bhi_ = (__int128)(ghi[0] + c.g) + (__int128)c.sy * (c.fold[1] * ghi[1] + c.g) +
+                        (__int128)c.sz * (c.fold[2] * ghi[2] + c.g);
+        const ExprL* ex = X->ex;
+        for (int e = 0; e < c.E; e++) {
+            int f = ex[e].f;
+            int64_t elem = c.elem ? c.elem : K.elem[f];
+            __int128 c0 = (__int128)ex[e].v[0] + (__int128)c.sy * ex[e].v[1] + (__int128)c.sz * ex[e].v[2];
+            __int128 a0 = (__int128)K.align[f] + (__int128)elem * (blo_ + c0);
+            __int128 a1 = (__int128)K.align[f] + (__int128)elem * (bhi_ + c0);
+            if (a0 < -LIM || a1 >= LIM) {
+                *bad = 1;
+                return;
+            }
+            if (first || a0 < lo) lo = a0;
+            if (first || a1 > hi) hi = a1;
+            first = false;
+        }
+    } else {
+        const ExprA* ex = (const ExprA*)K.items;
+        for (int e = 0; e < c.E; e++) {
+            __int128 a0 = ex[e].c0, a1 = ex[e].c0;
+            for (int d = 0; d < 3; d++) {
+                __int128 kt = (__int128)ex[e].ct[d] + ex[e].cg[d];
+                __int128 kb = (__int128)ex[e].cb[d] + (__int128)ex[e].cg[d] * c.b[d];
+                __int128 t0 = 0, t1 = kt * (c.b[d] - 1);
+                __int128 b0 = kb * blo[d], b1 = kb * bhi[d];
+                a0 += (t0 < t1 ? t0 : t1) + (b0 < b1 ? b0 : b1);
+                a1 += (t0 < t1 ? t1 : t0) + (b0 < b1 ? b1 : b0);
+            }
+            int f = ex[e].f;
+            __int128 A0 = (__int128)K.align[f] + (__int128)K.elem[f] * a0;
+            __int128 A1 = (__int128)K.align[f] + (__int128)K.elem[f] * a1;
+            if (A0 < -LIM || A1 >= LIM) {
+                *bad = 1;
+                return;
+            }
+            if (first || A0 < lo) lo = A0;
+            if (first || A1 > hi) hi = A1;
+            first = false;
+        }
+    }
+    *umin = (int64_t)lo >> log2u;
+    *umax = (int64_t)hi >> log2u;
+}
+
+__device__ int64_t round_cap(int64_t bound, int* log2cap)
+{
+    uint64_t want = (uint64_t)(bound > 32 ? bound : 32) * 2;
+    int l = bits_for(want - 1);
+    if (l > 40) l = 40;
+    *log2cap = l;
+    return (int64_t)1 << l;
+}
+
+__global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // space of configuration i
+    int lo = 0, hi = t.n_spaces - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (t.spaces[mid].first <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    const SpaceDev& S = t.spaces[lo];
+    const KernelDev& K = t.kernels[S.kernel_id];
+    const HwDev& H = t.hws[S.hw_id];
+    Cfg c;
+    memset(&c, 0, sizeof(c));
+    c.space = lo;
+    c.kernel_id = S.kernel_id;
+    c.hw_id = S.hw_id;
+    c.kind = S.kind;
+    c.expansion_id = -1;
+    c.smin = -1;
+    for (int d = 0; d < 3; d++) c.s[d] = -1;
+    int64_t local = i - S.first;
+    int64_t idx = S.explicit_idx ? S.explicit_idx[local] : local;
+    c.index = idx;
+    // mixed radix (outer, elem, fz, fy, shape), slowest first
+    int64_t r = idx;
+    int ish = (int)(r % S.n_shapes); r /= S.n_shapes;
+    int ify = (int)(r % S.n_fy); r /= S.n_fy;
+    int ifz = (int)(r % S.n_fz); r /= S.n_fz;
+    int iel = (int)(r % S.n_elem); r /= S.n_elem;
+    int iout = (int)r;
+    for (int d = 0; d < 3; d++) {
+        c.lb[d] = S.shapes[3 * ish + d];
+        c.b[d] = 1 << c.lb[d];
+        c.outer[d] = S.outer[3 * iout + d];
+    }
+    c.fold[0] = 1;
+    c.fold[1] = S.fy[ify];
+    c.fold[2] = S.fz[ifz];
+    c.elem = S.kind == 0 ? S.elem[iel] : 0;
+    c.P = (int64_t)c.b[0] * c.b[1] * c.b[2];
+    c.status = 0;
+    c.n_order = 0;
+    if (S.kind == 0) {
+        if (c.outer[0] <= 0 || c.outer[1] <= 0 || c.outer[2] <= 0 || c.outer[1] % c.fold[1] ||
+            c.outer[2] % c.fold[2]) {
+            c.status = -1;
+            cfgs[i] = c;
+            return;
+        }
+        c.T[0] = c.outer[0];
+        c.T[1] = c.outer[1] / c.fold[1];
+        c.T[2] = c.outer[2] / c.fold[2];
+        c.g = K.ghost;
+        c.sy = (int64_t)c.outer[0] + 2 * c.g;
+        c.sz = c.sy * ((int64_t)c.outer[1] + 2 * c.g);
+        c.expansion_id = S.exp_id[ify][ifz];
+        const Expansion& X = t.expansions[c.expansion_id];
+        c.E = X.E;
+        c.n_ld = X.n_ld;
+        c.uniform_elem = c.elem ? c.elem : K.uniform_elem;
+    } else {
+        if (c.outer[0] <= 0 || c.outer[1] <= 0 || c.outer[2] <= 0) {
+            c.status = -1;
+            cfgs[i] = c;
+            return;
+        }
+        for (int d = 0; d < 3; d++) c.T[d] = (int64_t)c.outer[d] * c.b[d];
+        c.E = K.n_items;
+        const ExprA* ex = (const ExprA*)K.items;
+        int nld = 0;
+        for (int e = 0; e < c.E; e++) nld += ex[e].st == 0;
+        c.n_ld = nld;
+        c.uniform_elem = K.uniform_elem;
+    }
+    for (int d = 0; d < 3; d++) c.nb[d] = (c.T[d] + c.b[d] - 1) / c.b[d];
+    int64_t occ = H.max_threads_per_cu / c.P;
+    if (occ > H.blocks_per_cu) occ = H.blocks_per_cu;
+    if (occ < 1) {
+        c.status = -1;
+        cfgs[i] = c;
+        return;
+    }
+    c.occ = occ;
+    c.N = (int64_t)H.n_cu * occ;
+    c.nbt = c.nb[0] * c.nb[1] * c.nb[2];
+    int64_t n_waves = (c.nbt + c.N - 1) / c.N;
+    c.w0 = (n_waves / 2) * c.N;
+    c.w1 = c.w0 + c.N < c.nbt ? c.w0 + c.N : c.nbt;
+    c.kB = c.nb[0] / 2 + c.nb[0] * (c.nb[1] / 2 + c.nb[1] * (c.nb[2] / 2));
+    c.segs_per_block = (int32_t)((c.P + kLanes - 1) / kLanes);
+    // layer sets: first block of the wave whose d-predecessor block lies
+    // before the wave; every block of the wave has a valid thread on its
+    // low face, so the predecessor of block k in d is k - stride_d
+    int64_t stride[3] = {1, c.nb[0], c.nb[0] * c.nb[1]};
+    for (int d = 0; d < 3; d++) {
+        int64_t kend = c.w0 + stride[d] < c.w1 ? c.w0 + stride[d] : c.w1;
+        for (int64_t k = c.w0; k < kend; k++) {
+            int64_t bd = (k / stride[d]) % c.nb[d];
+            if (bd >= 1) {
+                c.s[d] = k - stride[d];
+                break;
+            }
+        }
+        if (c.s[d] >= 0 && (c.smin < 0 || c.s[d] < c.smin)) c.smin = c.s[d];
+    }
+    // recency order: larger start first, ties x < y < z
+    for (int d = 0; d < 3; d++)
+        if (c.s[d] >= 0) c.order[c.n_order++] = d;
+    for (int a = 0; a < c.n_order; a++)
+        for (int b = a + 1; b < c.n_order; b++)
+            if (c.s[c.order[b]] > c.s[c.order[a]] ||
+                (c.s[c.order[b]] == c.s[c.order[a]] && c.order[b] < c.order[a])) {
+                int tmp = c.order[a];
+                c.order[a] = c.order[b];
+                c.order[b] = tmp;
+            }
+    // evaluations per pass and hash tables
+    int64_t nL = c.smin >= 0 ? c.w0 - c.smin : 0;
+    c.evals[PASS_B] = c.P * c.E;
+    c.evals[PASS_W] = (c.w1 - c.w0) * c.P * c.E;
+    c.evals[PASS_L] = nL * c.P * c.E;
+    c.tag_bits = bits_for((uint64_t)(nL + 1));
+    const Expansion* X = S.kind == 0 ? &t.expansions[c.expansion_id] : nullptr;
+    int bad = 0;
+    int64_t klo[N_TABLES] = {c.kB, c.kB, c.w0, c.w0, c.smin};
+    int64_t khi[N_TABLES] = {c.kB + 1, c.kB + 1, c.w1, c.w1, c.w0};
+    int gran[N_TABLES] = {H.log2_sector, H.log2_line, H.log2_sector, H.log2_line, H.log2_line};
+    int pbs[N_TABLES] = {0, 0, 2, 0, c.tag_bits};
+    int64_t ev[N_TABLES] = {(int64_t)c.P * c.n_ld, (int64_t)c.P * c.n_ld, c.evals[PASS_W],
+                            c.evals[PASS_W], c.evals[PASS_L]};
+    int64_t bytes = 0;
+    for (int q = 0; q < N_TABLES; q++) {
+        TableDesc& T = c.tab[q];
+        T.off = 0;
+        T.tag_off = -1;
+        T.log2cap = 0;
+        T.pb = pbs[q];
+        if (khi[q] <= klo[q] || klo[q] < 0 || ev[q] == 0) continue;
+        int64_t umin = 0, umax = 0;
+        unit_range(c, K, X, klo[q], khi[q], gran[q], &umin, &umax, &bad);
+        if (bad) break;
+        T.umin = umin;
+        T.span = umax - umin + 1;
+        uint64_t keys = (uint64_t)K.n_fields * (uint64_t)T.span;
+        if (T.span <= 0 || keys / (uint64_t)K.n_fields != (uint64_t)T.span ||
+            bits_for(keys) + T.pb > 64) {
+            bad = 1;
+            break;
+        }
+        int64_t bound = (int64_t)keys < ev[q] ? (int64_t)keys : ev[q];
+        int l2 = 0;
+        int64_t cap = round_cap(bound, &l2);
+        T.log2cap = l2;
+        T.off = bytes;
+        bytes += cap * 8;
+        if (q == T_WSEC) {
+            T.tag_off = bytes;
+            bytes += cap * 4;
+        }
+        bytes = (bytes + 255) & ~(int64_t)255;
+    }
+    // the layer pass keys its sectors with the wave table's layout and a tag
+    if (!bad && c.smin >= 0 && c.tab[T_WSEC].log2cap > 0) {
+        uint64_t keys = (uint64_t)K.n_fields * (uint64_t)c.tab[T_WSEC].span;
+        if (bits_for(keys) + c.tag_bits > 64) bad = 1;
+    }
+    if (c.tag_bits > 31) bad = 1;
+    if (bad) {
+        c.status = -3;
+        bytes = 0;
+    }
+    c.table_bytes = bytes;
+    cfgs[i] = c;
+}
+
+hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int64_t, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    int64_t blocks = (n + 127) / 128;
+    hipLaunchKernelGGL(k_decode, dim3((unsigned)blocks), dim3(128), 0, s, cfgs, n, t);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- fill zero
+
+__global__ void k_fill_zero(uint4* p, int64_t n16)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s)
+{
+    if (bytes <= 0) return hipSuccess;
+    int64_t n16 = (bytes + 15) / 16;   // callers pass 256-byte multiples
+    int64_t blocks = (n16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint4*)p, n16);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- evaluation
+
+__device__ __forceinline__ const WorkEntry* find_entry(const WorkEntry* work, int n_work,
+                                                       int64_t item)
+{
+    int lo = 0, hi = n_work - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) / 2;
+        if (work[mid].item_start <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return &work[lo];
+}
+
+// Distinct values of v among the valid lanes of each modelled warp of
+// 2^log2ws lanes (the warp's sectors of one instruction): one ballot per
+// distinct value.
+__device__ __forceinline__ int64_t warp_distinct(bool valid, int64_t v, int log2ws)
+{
+    uint64_t rem = __ballot(valid);
+    int64_t cnt = 0;
+    uint64_t wmask1 = log2ws >= 6 ? ~0ull : ((1ull << (1 << log2ws)) - 1);
+    while (rem) {
+        int l = __builtin_ctzll(rem);
+        int64_t val = readlane64(v, l);
+        uint64_t eq = __ballot(v == val);
+        uint64_t wm = log2ws >= 6 ? ~0ull : (wmask1 << ((l >> log2ws) << log2ws));
+        rem &= ~(eq & wm);
+        cnt++;
+    }
+    return cnt;
+}
+
+// L1 cycles of every group of 2^log2g lanes for one instruction (Sec. 4.2):
+// distinct bank words, greedy clusters of span < pair_words, each costing
+// its largest per-bank word count.  Returns the wave's total.
+__device__ __forceinline__ int64_t group_cycles(bool valid, int64_t w, int log2g, int nbanks,
+                                                int64_t pair_words)
+{
+    const int lane = lane_id();
+    const int gl = 1 << log2g;
+    const int glane = lane & (gl - 1);
+    const int gbase = lane - glane;
+    bool rep = valid;
+    for (int j = 1; j < gl; j++) {
+        int src = lane - j;
+        int64_t ow = shfl64(w, src < 0 ? 0 : src);
+        int ov = __shfl((int)valid, src < 0 ? 0 : src);
+        if (glane >= j && ov && ow == w) rep = false;
+    }
+    bool remn = rep;
+    int64_t cyc = 0;
+    while (__ballot(remn)) {
+        int64_t m = remn ? w : INT64_MAX;
+        for (int off = 1; off < gl; off <<= 1) {
+            int64_t o = shfl_xor64(m, off);
+            m = o < m ? o : m;
+        }
+        bool mem = remn && (w - m) < pair_words;
+        int bank = (int)(w & (int64_t)(nbanks - 1));
+        int mine = mem ? bank : -1;
+        int cnt = 0;
+        for (int j = 0; j < gl; j++) {
+            int ob = __shfl(mine, gbase + j);
+            cnt += (mem && ob == bank) ? 1 : 0;
+        }
+        for (int off = 1; off < gl; off <<= 1) {
+            int o = __shfl_xor(cnt, off);
+            cnt = o > cnt ? o : cnt;
+        }
+        if (glane == 0) cyc += cnt;
+        remn = remn && !mem;
+    }
+    return wave_sum64(cyc);
+}
+
+struct PassCtx {
+    const Cfg* c;
+    const KernelDev* K;
+    const HwDev* H;
+    const ExprL* exl;
+    const ExprA* exa;
+    char* arena;
+    unsigned long long* set0;
+    unsigned long long* set1;
+    uint64_t lmask;
+    int lslots;
+    int fill0, fill1;
+    uint64_t err;
+};
+
+// move every entry of a per-wave LDS set into the configuration's HBM table
+__device__ void flush_set(PassCtx& P, unsigned long long* set, int q, int mode, bool probe_wsec)
+{
+    const TableDesc& T = P.c->tab[q];
+    unsigned long long* slots = (unsigned long long*)(P.arena + T.off);
+    uint64_t mask = ((uint64_t)1 << T.log2cap) - 1;
+    int lane = lane_id();
+    bool overflow = false;
+    for (int i = lane; i < P.lslots; i += kLanes) {
+        unsigned long long e = set[i];
+        if (e == 0) continue;
+        set[i] = 0;
+        if (!probe_wsec) {
+            if (set_insert<false>(slots, mask, e, T.pb, mode) < 0) overflow = true;
+        } else {
+            // layer sector with its block tag, probed in the wave sector table
+            int tb = P.c->tag_bits;
+            uint64_t key1 = e >> tb;
+            unsigned tag = (unsigned)(e & (((uint64_t)1 << tb) - 1));
+            const TableDesc& W = P.c->tab[T_WSEC];
+            const unsigned long long* ws = (const unsigned long long*)(P.arena + W.off);
+            int64_t pos = set_find(ws, ((uint64_t)1 << W.log2cap) - 1, key1, W.pb);
+            if (pos >= 0) {
+                unsigned* tags = (unsigned*)(P.arena + W.tag_off);
+                atomicMax(&tags[pos], tag);
+            }
+        }
+    }
+    if (__ballot(overflow)) P.err |= 2;
+    wave_fence();
+}
+
+// insert one entry per valid lane into a per-wave LDS set; a lane whose left
+// neighbour holds the same entry skips (the set would merge it anyway)
+__device__ __forceinline__ int lds_add(PassCtx& P, unsigned long long* set, bool active,
+                                       uint64_t entry, int pb, int mode)
+{
+    int lane = lane_id();
+    int64_t prev = shfl64((int64_t)entry, lane > 0 ? lane - 1 : 0);
+    int pact = __shfl((int)active, lane > 0 ? lane - 1 : 0);
+    bool lead = active && !(lane > 0 && pact && (uint64_t)prev == entry);
+    int got = 0;
+    if (lead) got = set_insert<true>(set, P.lmask, entry, pb, mode);
+    return __popcll(__ballot(got == 1));
+}
+
+template <int PASS, int KIND>
+__device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, int64_t j1)
+{
+    const Cfg& c = *P.c;
+    const KernelDev& K = *P.K;
+    const HwDev& H = *P.H;
+    const int lane = lane_id();
+    const int spb = c.segs_per_block;
+    const int thr = P.lslots / 2 - kLanes;
+    int64_t acc_up_ld = 0, acc_up_st = 0, acc_cyc = 0, acc_lanes = 0, acc_warps = 0;
+    const TableDesc& TS = c.tab[PASS == PASS_W ? T_WSEC : (PASS == PASS_B ? T_BSEC : T_WSEC)];
+    const TableDesc& TL = c.tab[PASS == PASS_W ? T_WLINE : (PASS == PASS_B ? T_BLINE : T_LLINE)];
+    const int ls = H.log2_sector, ll = H.log2_line;
+    const int sec_pb = PASS == PASS_W ? 2 : (PASS == PASS_L ? c.tag_bits : 0);
+    const int line_pb = PASS == PASS_L ? c.tag_bits : 0;
+    const int sec_mode = PASS == PASS_W ? MODE_OR : (PASS == PASS_L ? MODE_MAX : MODE_SET);
+    const int line_mode = PASS == PASS_L ? MODE_MAX : MODE_SET;
+    const bool do_sec = TS.log2cap > 0;
+
+    for (int64_t j = j0; j < j1; j++) {
+        int64_t k = k_lo + j / spb;
+        int64_t sgi = j % spb;
+        int64_t bid[3];
+        bid[0] = k % c.nb[0];
+        bid[1] = (k / c.nb[0]) % c.nb[1];
+        bid[2] = k / (c.nb[0] * c.nb[1]);
+        int64_t t = sgi * kLanes + lane;
+        bool inb = t < c.P;
+        int64_t tid[3];
+        tid[0] = t & (c.b[0] - 1);
+        tid[1] = (t >> c.lb[0]) & (c.b[1] - 1);
+        tid[2] = t >> (c.lb[0] + c.lb[1]);
+        int64_t gid[3];
+        for (int d = 0; d < 3; d++) gid[d] = bid[d] * c.b[d] + tid[d];
+        bool valid = inb && gid[0] < c.T[0] && gid[1] < c.T[1] && gid[2] < c.T[2];
+        uint64_t vmask = __ballot(valid);
+        acc_lanes += __popcll(vmask);
+        if (PASS == PASS_B) {
+            // modelled warps of this segment with a valid lane
+            int ws = 1 << H.log2_warp;
+            for (int w = 0; w < kLanes; w += ws) {
+                uint64_t m = ws >= 64 ? ~0ull : (((1ull << ws) - 1) << w);
+                if (vmask & m) acc_warps++;
+            }
+        }
+        if (vmask == 0) continue;
+        uint64_t tag = PASS == PASS_L ? (uint64_t)(k - c.smin + 1) : 0;
+        int64_t base = 0;
+        if (KIND == 0)
+            base = (gid[0] + c.g) + c.sy * (c.fold[1] * gid[1] + c.g) + c.sz * (c.fold[2] * gid[2] + c.g);
+        int64_t ubase = c.uniform_elem ? base * c.uniform_elem : 0;
+
+        for (int e = 0; e < c.E; e++) {
+            int f, st;
+            int64_t addr;
+            if (KIND == 0) {
+                const ExprL x = P.exl[e];
+                f = x.f;
+                st = x.st;
+                int64_t c0 = (int64_t)x.v[0] + c.sy * x.v[1] + c.sz * x.v[2];
+                if (c.uniform_elem) {
+                    addr = ubase + (K.align[f] + (int64_t)c.uniform_elem * c0);
+                } else {
+                    int64_t elem = c.elem ? c.elem : K.elem[f];
+                    addr = K.align[f] + elem * (base + c0);
+                }
+            } else {
+                const ExprA& x = P.exa[e];
+                f = x.f;
+                st = x.st;
+                int64_t idx = x.c0;
+                for (int d = 0; d < 3; d++)
+                    idx += (x.ct[d] + x.cg[d]) * tid[d] + (x.cb[d] + x.cg[d] * c.b[d]) * bid[d];
+                addr = K.align[f] + (int64_t)K.elem[f] * idx;
+            }
+            if (PASS == PASS_B && (P.fill0 > thr || P.fill1 > thr)) {
+                flush_set(P, P.set0, T_BSEC, MODE_SET, false);
+                flush_set(P, P.set1, T_BLINE, MODE_SET, false);
+                P.fill0 = P.fill1 = 0;
+            }
+            if (PASS == PASS_W && (P.fill0 > thr || P.fill1 > thr)) {
+                flush_set(P, P.set0, T_WSEC, MODE_OR, false);
+                flush_set(P, P.set1, T_WLINE, MODE_SET, false);
+                P.fill0 = P.fill1 = 0;
+            }
+            if (PASS == PASS_L && (P.fill0 > thr || P.fill1 > thr)) {
+                flush_set(P, P.set0, T_WSEC, MODE_MAX, true);
+                flush_set(P, P.set1, T_LLINE, MODE_MAX, false);
+                P.fill0 = P.fill1 = 0;
+            }
+            int64_t sec = addr >> ls;
+            int64_t line = addr >> ll;
+            if (PASS == PASS_B) {
+                int64_t dcount = warp_distinct(valid, sec, H.log2_warp);
+                if (st) acc_up_st += dcount;
+                else acc_up_ld += dcount;
+                acc_cyc += group_cycles(valid, addr >> H.log2_bank, H.log2_group, H.l1_banks,
+                                        H.pair_words);
+                if (!st) {
+                    int64_t us = sec - TS.umin, ul = line - TL.umin;
+                    bool ok = (uint64_t)us < (uint64_t)TS.span && (uint64_t)ul < (uint64_t)TL.span;
+                    if (__ballot(valid && !ok)) P.err |= 1;
+                    bool act = valid && ok;
+                    uint64_t ks = (uint64_t)((int64_t)f * TS.span + us + 1);
+                    uint64_t kl = (uint64_t)((int64_t)f * TL.span + ul + 1);
+                    P.fill0 += lds_add(P, P.set0, act, ks, 0, MODE_SET);
+                    P.fill1 += lds_add(P, P.set1, act, kl, 0, MODE_SET);
+                }
+            } else if (PASS == PASS_W) {
+                if (st) acc_up_st += warp_distinct(valid, sec, H.log2_warp);
+                int64_t us = sec - TS.umin, ul = line - TL.umin;
+                bool ok = (uint64_t)us < (uint64_t)TS.span && (uint64_t)ul < (uint64_t)TL.span;
+                if (__ballot(valid && !ok)) P.err |= 1;
+                bool act = valid && ok;
+                uint64_t ks = ((uint64_t)((int64_t)f * TS.span + us + 1) << 2) | (st ? 2u : 1u);
+                uint64_t kl = (uint64_t)((int64_t)f * TL.span + ul + 1);
+                P.fill0 += lds_add(P, P.set0, act, ks, sec_pb, sec_mode);
+                P.fill1 += lds_add(P, P.set1, act, kl, line_pb, line_mode);
+            } else {
+                int64_t ul = line - TL.umin;
+                bool ok = (uint64_t)ul < (uint64_t)TL.span;
+                if (__ballot(valid && !ok)) P.err |= 1;
+                uint64_t kl = ((uint64_t)((int64_t)f * TL.span + ul + 1) << line_pb) | tag;
+                P.fill1 += lds_add(P, P.set1, valid && ok, kl, line_pb, line_mode);
+                if (do_sec) {
+                    int64_t us = sec - TS.umin;
+                    bool in = (uint64_t)us < (uint64_t)TS.span;
+                    uint64_t ks = ((uint64_t)((int64_t)f * TS.span + us + 1) << sec_pb) | tag;
+                    P.fill0 += lds_add(P, P.set0, valid && in, ks, sec_pb, sec_mode);
+                }
+            }
+        }
+    }
+    // final flush and accumulators
+    if (PASS == PASS_B) {
+        flush_set(P, P.set0, T_BSEC, MODE_SET, false);
+        flush_set(P, P.set1, T_BLINE, MODE_SET, false);
+    } else if (PASS == PASS_W) {
+        flush_set(P, P.set0, T_WSEC, MODE_OR, false);
+        flush_set(P, P.set1, T_WLINE, MODE_SET, false);
+    } else {
+        if (do_sec) flush_set(P, P.set0, T_WSEC, MODE_MAX, true);
+        flush_set(P, P.set1, T_LLINE, MODE_MAX, false);
+    }
+    if (lane == 0) {
+        if (PASS == PASS_B) {
+            atomicAdd(&ctr->lanes_B, (unsigned long long)acc_lanes);
+            atomicAdd(&ctr->warps_B, (unsigned long long)acc_warps);
+            atomicAdd(&ctr->up_ld_B, (unsigned long long)acc_up_ld);
+            atomicAdd(&ctr->up_st_B, (unsigned long long)acc_up_st);
+            atomicAdd(&ctr->l1_cycles_B, (unsigned long long)acc_cyc);
+        } else if (PASS == PASS_W) {
+            atomicAdd(&ctr->lanes_W, (unsigned long long)acc_lanes);
+            atomicAdd(&ctr->up_st_W, (unsigned long long)acc_up_st);
+        } else {
+            atomicAdd(&ctr->lanes_L, (unsigned long long)acc_lanes);
+        }
+        if (P.err) atomicOr(&ctr->err, (unsigned long long)P.err);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_eval(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr,
+                                              const WorkEntry* work, int n_work, int64_t n_items,
+                                              char* arena, DevTables t, int lds_slots)
+{
+    extern __shared__ unsigned long long lds[];
+    const int wave = (int)(threadIdx.x >> 6);
+    const int lane = lane_id();
+    const int64_t n_waves = (int64_t)gridDim.x * kWavesPerGroup;
+    for (int64_t item = (int64_t)blockIdx.x * kWavesPerGroup + wave; item < n_items; item += n_waves) {
+    const WorkEntry* W = find_entry(work, n_work, item);
+    const Cfg& c = cfgs[W->cfg];
+    int64_t local = item - W->item_start;
+    int64_t j0 = local * W->per_item;
+    int64_t j1 = j0 + W->per_item < W->n_units ? j0 + W->per_item : W->n_units;
+
+    PassCtx P;
+    P.c = &c;
+    P.K = &t.kernels[c.kernel_id];
+    P.H = &t.hws[c.hw_id];
+    P.exl = c.kind == 0 ? t.expansions[c.expansion_id].ex : nullptr;
+    P.exa = c.kind == 1 ? (const ExprA*)P.K->items : nullptr;
+    P.arena = arena + cfg_base[W->cfg];
+    P.set0 = lds + (size_t)wave * 2 * lds_slots;
+    P.set1 = P.set0 + lds_slots;
+    P.lslots = lds_slots;
+    P.lmask = (uint64_t)lds_slots - 1;
+    P.fill0 = P.fill1 = 0;
+    P.err = 0;
+    for (int i = lane; i < 2 * lds_slots; i += kLanes) P.set0[i] = 0;
+    wave_fence();
+    Counters* cc = &ctr[W->cfg];
+    int pass = W->what;
+    if (c.kind == 0) {
+        if (pass == PASS_B) run_pass<PASS_B, 0>(P, cc, c.kB, j0, j1);
+        else if (pass == PASS_W) run_pass<PASS_W, 0>(P, cc, c.w0, j0, j1);
+        else run_pass<PASS_L, 0>(P, cc, c.smin, j0, j1);
+    } else {
+        if (pass == PASS_B) run_pass<PASS_B, 1>(P, cc, c.kB, j0, j1);
+        else if (pass == PASS_W) run_pass<PASS_W, 1>(P, cc, c.w0, j0, j1);
+        else run_pass<PASS_L, 1>(P, cc, c.smin, j0, j1);
+    }
+    }
+}
+
+hipError_t launch_eval(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr, const WorkEntry* work,
+                       int n_work, int64_t n_items, char* arena, DevTables t, int lds_slots,
+                       int64_t max_groups, hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    int64_t groups = (n_items + kWavesPerGroup - 1) / kWavesPerGroup;
+    if (groups > max_groups) groups = max_groups;
+    size_t shm = (size_t)kWavesPerGroup * 2 * lds_slots * sizeof(unsigned long long);
+    hipLaunchKernelGGL(k_eval, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup), shm, s, cfgs,
+                       cfg_base, ctr, work, n_work, n_items, arena, t, lds_slots);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- counting
+
+__global__ __launch_bounds__(256) void k_count(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr,
+                                               const WorkEntry* work, int n_work, int64_t n_items,
+                                               const char* arena_all)
+{
+    const int wave = (int)(threadIdx.x >> 6);
+    const int lane = lane_id();
+    const int64_t n_waves = (int64_t)gridDim.x * kWavesPerGroup;
+    for (int64_t item = (int64_t)blockIdx.x * kWavesPerGroup + wave; item < n_items; item += n_waves) {
+    const WorkEntry* W = find_entry(work, n_work, item);
+    const Cfg& c = cfgs[W->cfg];
+    const char* arena = arena_all + cfg_base[W->cfg];
+    int q = W->what;
+    const TableDesc& T = c.tab[q];
+    const unsigned long long* slots = (const unsigned long long*)(arena + T.off);
+    int64_t local = item - W->item_start;
+    int64_t i0 = local * W->per_item;
+    int64_t i1 = i0 + W->per_item < W->n_units ? i0 + W->per_item : W->n_units;
+    int64_t n0 = 0, n1 = 0, sh[3] = {0, 0, 0}, ll[3] = {0, 0, 0};
+    const unsigned* tags = q == T_WSEC ? (const unsigned*)(arena + T.tag_off) : nullptr;
+    uint64_t pmask = ((uint64_t)1 << T.pb) - 1;
+    for (int64_t i = i0 + lane; i < i1; i += kLanes) {
+        unsigned long long e = slots[i];
+        if (e == 0) continue;
+        if (q == T_WSEC) {
+            bool ld = (e & 1) != 0;
+            n0 += ld;
+            n1 += (e & 2) != 0;
+            if (ld && c.n_order > 0) {
+                unsigned tg = tags[i];
+                int64_t last = tg ? c.smin + (int64_t)tg - 1 : -1;
+                for (int a = 0; a < c.n_order; a++) {
+                    int d = c.order[a];
+                    bool in_d = last >= c.s[d];
+                    bool in_prev = a > 0 && last >= c.s[c.order[a - 1]];
+                    sh[d] += in_d && !in_prev;
+                }
+            }
+        } else if (q == T_LLINE) {
+            int64_t blk = c.smin + (int64_t)(e & pmask) - 1;
+            for (int d = 0; d < 3; d++) ll[d] += c.s[d] >= 0 && blk >= c.s[d];
+        } else {
+            n0++;
+        }
+    }
+    n0 = wave_sum64(n0);
+    n1 = wave_sum64(n1);
+    for (int d = 0; d < 3; d++) {
+        sh[d] = wave_sum64(sh[d]);
+        ll[d] = wave_sum64(ll[d]);
+    }
+    if (lane == 0) {
+        Counters* cc = &ctr[W->cfg];
+        if (q == T_BSEC) atomicAdd(&cc->comp_ld_B, (unsigned long long)n0);
+        else if (q == T_BLINE) atomicAdd(&cc->lines_ld_B, (unsigned long long)n0);
+        else if (q == T_WLINE) atomicAdd(&cc->lines_W, (unsigned long long)n0);
+        else if (q == T_WSEC) {
+            atomicAdd(&cc->fpld_W, (unsigned long long)n0);
+            atomicAdd(&cc->comp_st_W, (unsigned long long)n1);
+            for (int d = 0; d < 3; d++)
+                if (sh[d]) atomicAdd(&cc->shell[d], (unsigned long long)sh[d]);
+        } else {
+            for (int d = 0; d < 3; d++)
+                if (ll[d]) atomicAdd(&cc->lines_L[d], (unsigned long long)ll[d]);
+        }
+    }
+    }
+}
+
+hipError_t launch_count(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr, const WorkEntry* work,
+                        int n_work, int64_t n_items, const char* arena, int64_t max_groups,
+                        hipStream_t s)
+{
+    if (n_items == 0) return hipSuccess;
+    int64_t groups = (n_items + kWavesPerGroup - 1) / kWavesPerGroup;
+    if (groups > max_groups) groups = max_groups;
+    hipLaunchKernelGGL(k_count, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup), 0, s, cfgs,
+                       cfg_base, ctr, work, n_work, n_items, arena);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ model
+
+// exp(x): Cody & Waite reduction x = k*ln2 + r with ln 2 split into a head
+// of 32 significant bits and a tail, then e^r by its Taylor polynomial of
+// degree 13 in Horner form with fused multiply-adds, scaled by 2^k.
+__device__ double dev_exp(double x)
+{
+    if (x != x) return x;
+    if (x > 710.0) return __builtin_inf();
+    if (x < -746.0) return 0.0;
+    const double kInvLn2 = 0x1.71547652b82fep+0;
+    const double kLn2Hi = 0x1.62e42ffp-1;
+    const double kLn2Lo = -0x1.718432a1b0e26p-35;
+    // 1/n! for n = 0..13, each folded by the compiler as one correctly rounded quotient
+    constexpr double kInvFact[14] = {1.0 / 1.0, 1.0 / 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0,
+                                     1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0,
+                                     1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0,
+                                     1.0 / 479001600.0, 1.0 / 6227020800.0};
+    double k = __builtin_rint(x * kInvLn2);
+    double r = __builtin_fma(-k, kLn2Hi, x);
+    r = __builtin_fma(-k, kLn2Lo, r);
+    double p = kInvFact[13];
+#pragma unroll
+    for (int n = 12; n >= 0; n--) p = __builtin_fma(p, r, kInvFact[n]);
+    return __builtin_ldexp(p, (int)k);
+}
+
+// hit rate of redundant volume at oversubscription O: a*exp(-b*exp(c*O));
+// b = 0 gives the constant a
+__device__ double dev_rhat(const double* fit, double O)
+{
+    if (fit[1] == 0.0) return fit[0];
+    double e1 = dev_exp(fit[2] * O);
+    double t = fit[1] * e1;
+    return fit[0] * dev_exp(-t);
+}
+
+__global__ void k_reduce(const Cfg* cfgs, const Counters* ctr, int64_t n, DevTables t, Result* out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Cfg& c = cfgs[i];
+    const Counters& k = ctr[i];
+    Result r;
+    memset(&r, 0, sizeof(r));
+    r.index = c.index;
+    for (int d = 0; d < 3; d++) {
+        r.shape[d] = c.b[d];
+        r.fold[d] = c.fold[d];
+        r.domain[d] = c.outer[d];
+        r.s_layer[d] = -1;
+    }
+    r.elem = c.elem;
+    r.limiter = -1;
+    int status = c.status;
+    if (status == 0 && (k.err & 1)) status = -3;
+    if (status == 0 && (k.err & 2)) status = -2;
+    if (status != 0) {
+        r.status = status;
+        out[i] = r;
+        return;
+    }
+    const HwDev& H = t.hws[c.hw_id];
+    const KernelDev& K = t.kernels[c.kernel_id];
+    int64_t lpt = (int64_t)c.fold[1] * c.fold[2];
+    r.n_expr = c.E;
+    r.lups_B = (int64_t)k.lanes_B * lpt;
+    r.warps_B = (int64_t)k.warps_B;
+    r.l1_cycles_B = (int64_t)k.l1_cycles_B;
+    r.up_ld_B = (int64_t)k.up_ld_B;
+    r.up_st_B = (int64_t)k.up_st_B;
+    r.comp_ld_B = (int64_t)k.comp_ld_B;
+    r.lines_ld_B = (int64_t)k.lines_ld_B;
+    r.blocks_W = c.w1 - c.w0;
+    r.lups_W = (int64_t)k.lanes_W * lpt;
+    r.fpld_W = (int64_t)k.fpld_W;
+    r.comp_st_W = (int64_t)k.comp_st_W;
+    r.up_st_W = (int64_t)k.up_st_W;
+    r.lines_W = (int64_t)k.lines_W;
+    for (int d = 0; d < 3; d++) {
+        r.s_layer[d] = c.s[d];
+        r.lines_L[d] = c.s[d] >= 0 ? (int64_t)k.lines_L[d] : 0;
+        r.shell[d] = c.s[d] >= 0 ? (int64_t)k.shell[d] : 0;
+    }
+    // capacity misses (Sec. 4.5)
+    r.O_l1 = (double)(c.occ * r.lines_ld_B * H.line_bytes) / (double)H.l1_bytes;
+    r.R_l1 = dev_rhat(H.fit[0], r.O_l1);
+    r.v_l2l1_ld = (double)r.comp_ld_B + (1.0 - r.R_l1) * (double)(r.up_ld_B - r.comp_ld_B);
+    int64_t fresh = r.fpld_W;
+    for (int d = 0; d < 3; d++) {
+        if (c.s[d] < 0) continue;
+        r.O_L[d] = (double)(H.line_bytes * r.lines_L[d]) / (double)H.l2_bytes;
+        r.R_L[d] = dev_rhat(d == 2 ? H.fit[2] : H.fit[1], r.O_L[d]);
+        fresh -= r.shell[d];
+    }
+    r.O_W = (double)(H.line_bytes * r.lines_W) / (double)H.l2_bytes;
+    r.R_st = dev_rhat(H.fit[3], r.O_W);
+    double v = (double)fresh;
+    for (int d = 0; d < 3; d++) v = v + (1.0 - r.R_L[d]) * (double)r.shell[d];
+    v = v + (1.0 - r.R_st) * (double)(r.up_st_W - r.comp_st_W);
+    r.v_dram_ld = v;
+    r.v_dram_st = (double)r.comp_st_W;
+    // four limiters (Sec. 2)
+    double sector = (double)H.sector_bytes;
+    const double inf = __builtin_inf();
+    r.bpl_l2 = sector * (r.v_l2l1_ld + (double)r.up_st_B) / (double)r.lups_B;
+    r.bpl_dram = sector * (r.v_dram_ld + r.v_dram_st) / (double)r.lups_W;
+    r.p_l1 = r.l1_cycles_B > 0 ? (double)r.lups_B * (double)H.n_cu * H.clock_hz / (double)r.l1_cycles_B
+                               : inf;
+    r.p_l2 = r.bpl_l2 > 0.0 ? H.bw_l2 / r.bpl_l2 : inf;
+    r.p_dram = r.bpl_dram > 0.0 ? H.bw_dram / r.bpl_dram : inf;
+    r.p_fp = (K.flops_per_lup > 0.0 && H.flops_peak > 0.0) ? H.flops_peak / K.flops_per_lup : inf;
+    double p[4] = {r.p_l1, r.p_l2, r.p_dram, r.p_fp};
+    int lim = 0;
+    for (int q = 1; q < 4; q++)
+        if (p[q] < p[lim]) lim = q;
+    r.limiter = lim;
+    r.perf = p[lim];
+    r.status = 0;
+    out[i] = r;
+}
+
+hipError_t launch_reduce(const Cfg* cfgs, const Counters* ctr, int64_t n, DevTables t, Result* out,
+                         hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, cfgs, ctr, n, t,
+                       out);
+    return hipGetLastError();
+}
+
+__global__ void k_rhat(double a, double b, double c, const double* O, double* R, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double fit[3] = {a, b, c};
+    R[i] = dev_rhat(fit, O[i]);
+}
+
+hipError_t launch_rhat(const double* fit, const double* O, double* R, int64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rhat, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fit[0], fit[1], fit[2],
+                       O, R, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- rank
+
+__global__ void k_rank(const Result* res, const int64_t* space_first, const int32_t* cfg_space,
+                       int64_t n, int32_t* rank)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int sp = cfg_space[i];
+    int64_t lo = space_first[sp], hi = space_first[sp + 1];
+    double p = res[i].perf;
+    int64_t idx = res[i].index;
+    int64_t r = 0;
+    for (int64_t j = lo; j < hi; j++) {
+        double q = res[j].perf;
+        r += (q > p) || (q == p && res[j].index < idx);
+    }
+    rank[i] = (int32_t)r;
+}
+
+hipError_t launch_rank(const Result* res, const int64_t* space_first, const int32_t* cfg_space,
+                       int64_t n, int32_t* rank, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rank, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, res, space_first,
+                       cfg_space, n, rank);
+    return hipGetLastError();
+}
+
+}  // namespace wse

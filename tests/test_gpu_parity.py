@@ -1,0 +1,144 @@
+"""Parity of the HIP library with the CPU oracle: every field of every
+configuration bit-identical (integers exactly, doubles bitwise), ranks
+identical.  Inputs are the seeded workloads; expected values come from the
+oracle, live or stored by tests/golden/make_golden.py."""
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2204_14242_amd import workloads as W
+from gpu_common import assert_same, gpu_available, run_gpu, run_oracle
+from helpers import TINY_HW, with_hw
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_2204_14242_amd import wsest
+    c = wsest.Context(0, arena_bytes=8 << 30)
+    yield c
+    c.close()
+
+
+def check(ctx, orc, specs, label, mode=1):
+    say(f"case {label}: {sum(len(s[2]['explicit']) if s[2].get('explicit') else 0 for s in specs)} explicit configs")
+    got, grank = run_gpu(ctx, specs, mode)
+    want, wrank = run_oracle(orc, specs)
+    assert_same(got, want, grank, wrank, label)
+    return got
+
+
+def test_rhat_bitwise(ctx, orc):
+    rng = np.random.default_rng(7)
+    O = np.concatenate([rng.uniform(0, 4, 50000), rng.uniform(0, 300, 20000),
+                        np.array([0.0, 1e-300, 0.5, 1.0, 2.0, 1e3, 1e6, np.inf])])
+    for fit in [W.FIT_L1, W.FIT_L2_Y, W.FIT_L2_Z, W.FIT_L2_STORE, (1.0, 1.0, 1.0),
+                (0.7, 2.5, 0.01), (1.0, 0.0, 3.0), (0.0, 0.5, 1.0), (1.0, 1e-9, 50.0)]:
+        say(f"case rhat fit={fit}")
+        got = ctx.rhat(fit, O)
+        want = np.array([orc.rhat(fit, float(o)) for o in O])
+        assert got.tobytes() == want.tobytes(), fit
+
+
+def test_stencil_64_sample(ctx, orc):
+    k, hw, sp = W.stencil_plain()
+    sp = dict(sp, domains=[(64, 64, 64)], explicit=list(range(0, 230, 7)))
+    check(ctx, orc, [(k, hw, sp)], "stencil 64^3")
+
+
+def test_stencil_folding_and_elements(ctx, orc):
+    k = W.star_stencil(4)
+    sp = W.lattice_space([(64, 64, 64), (32, 64, 128)], min_threads=32, max_threads=1024,
+                         fy=(1, 2, 4), fz=(1, 2, 8), elems=[4, 8])
+    rng = random.Random(3)
+    n = 2 * 2 * 3 * 3 * 251
+    sp["explicit"] = sorted(rng.sample(range(n), 60))
+    check(ctx, orc, [(k, W.HW1, sp)], "stencil folds/elems")
+
+
+def test_lbm_small(ctx, orc):
+    k = W.lbm_two_phase(8)
+    sp = W.lattice_space([(32, 32, 32)], min_threads=32, max_threads=1024, fy=(1, 2), fz=(1, 2),
+                         elems=[8])
+    rng = random.Random(4)
+    sp["explicit"] = sorted(rng.sample(range(4 * 251), 16))
+    check(ctx, orc, [(k, W.HW1, sp)], "lbm 32^3")
+
+
+def test_random_affine_tiny(ctx, orc):
+    specs = []
+    for seed in range(6):
+        rng = random.Random(300 + seed)
+        nf = rng.randint(1, 3)
+        fields = [(rng.choice([4, 8]), rng.choice([0, 8, 24, 200, -64])) for _ in range(nf)]
+        exprs = []
+        for _ in range(rng.randint(2, 9)):
+            f = rng.randrange(nf)
+            m = (1, 29 + f, 400 + 3 * f)
+            exprs.append((f, int(rng.random() < 0.3), rng.randint(-40, 40),
+                          *[rng.randint(-4, 4) * m[d] for d in range(3)],
+                          *[rng.randint(-4, 4) * m[d] for d in range(3)],
+                          *[rng.randint(-2, 2) * m[d] for d in range(3)]))
+        hw = with_hw(TINY_HW, warp_size=rng.choice([4, 8, 16]), n_cu=rng.randint(1, 3),
+                     l1_group_lanes=rng.choice([1, 2, 4]))
+        sp = W.affine_space([(rng.randint(1, 5), rng.randint(1, 3), rng.randint(1, 4)), (2, 3, 2)],
+                            min_threads=2, max_threads=64, exps=range(5))
+        specs.append((W.affine_kernel(fields, exprs), hw, sp))
+    check(ctx, orc, specs, "random affine")
+
+
+def test_stress_sample(ctx, orc):
+    spaces = W.stress_spaces(seed=5, total=60, max_space=20)
+    check(ctx, orc, spaces[:4], "stress sample")
+
+
+def test_edge_cases(ctx, orc):
+    specs = []
+    # warp 32 hardware, ghost layers, a negative alignment
+    k = W.star_stencil(2, align=-256, ghost=2)
+    sp = W.lattice_space([(40, 24, 16)], min_threads=1, max_threads=1024, fy=(1, 2), fz=(1, 4),
+                         exps=range(7))
+    sp["explicit"] = list(range(0, 2 * 2 * 84, 9))
+    specs.append((k, W.H2, sp))
+    # blocks far larger than the domain, single-wave grids, reversed explicit order
+    sp2 = W.lattice_space([(8, 8, 8), (200, 3, 5)], min_threads=32, max_threads=1024, elems=[4])
+    sp2["explicit"] = list(range(2 * 251 - 1, -1, -13))
+    specs.append((W.star_stencil(4), W.HW1, sp2))
+    # invalid configurations: folding that does not divide, blocks above the CU limit
+    sp3 = W.lattice_space([(64, 60, 60)], min_threads=256, max_threads=1024, fy=(1, 8), fz=(1, 8))
+    specs.append((W.star_stencil(1), with_hw(W.HW1, max_threads_per_cu=512), sp3))
+    got = check(ctx, orc, specs, "edge cases")
+    assert (got["status"] == -1).any() and (got["status"] == 0).any()
+
+
+def test_plain_equals_batched(ctx, orc):
+    k, hw, sp = W.stencil_plain()
+    sp = dict(sp, domains=[(64, 64, 64)], explicit=list(range(3, 230, 17)))
+    say("case plain vs batched")
+    a, ra = run_gpu(ctx, [(k, hw, sp)], mode=0)
+    b, rb = run_gpu(ctx, [(k, hw, sp)], mode=1)
+    assert a.tobytes() == b.tobytes() and np.array_equal(ra, rb)
+
+
+def test_stencil_plain_256_golden(ctx):
+    path = os.path.join(HERE, "golden", "stencil_plain_256.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    g = np.load(path, allow_pickle=False)
+    k, hw, sp = W.stencil_plain()
+    say("case stencil 256^3 all 230 configs vs stored oracle values")
+    got, rank = run_gpu(ctx, [(k, hw, sp)])
+    assert_same(got, g["results"], rank, g["rank"], "stencil 256^3 golden")
