@@ -31,7 +31,7 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1)
-    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--warmup", type=int, default=0)
     p.add_argument("--mode", choices=["batched", "plain"], default="batched")
     p.add_argument("--workload", choices=["stencil_batched", "stencil_plain", "lbm_batched"],
                    default="stencil_batched")
@@ -84,6 +84,8 @@ def main():
               "spaces would shard by configuration range across GPUs, which this build does not do",
               file=sys.stderr)
         sys.exit(2)
+    # one progress line per arena round on stderr, so long steps keep printing
+    os.environ.setdefault("WSE_PROGRESS", "1")
     import numpy as np
     import torch
 

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -105,7 +107,7 @@ struct wse_ctx {
     DevBuf<Result> d_res;
     DevBuf<int32_t> d_rank;
     DevBuf<ExpandJob> d_jobs;
-    int lds_slots = 1024;
+    int lds_slots = 512;
     int64_t target_evals = 1 << 17;
     double timings[8] = {0};
     bool dirty_kernels = false, dirty_hws = false;
@@ -113,6 +115,7 @@ struct wse_ctx {
     std::vector<int64_t> base;   // arena offset of each configuration's tables
     // statistics of the last call
     int64_t last_total = 0, last_table_bytes = 0, last_launches = 0, last_rounds = 0;
+    bool progress = false;   // WSE_PROGRESS=1: one stderr line per arena round
     std::vector<int32_t> last_E;
 };
 
@@ -154,6 +157,8 @@ wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out)
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    const char* pg = std::getenv("WSE_PROGRESS");
+    c->progress = pg && pg[0] == '1';
     *out = c;
     return WSE_OK;
 }
@@ -652,6 +657,9 @@ static wse_status run_rounds(wse_ctx* c, const std::vector<Cfg>& cfgs, const std
         HIP_TRY(hipStreamSynchronize(st));
         *eval_ms += elapsed(e0, e1);
         *count_ms += elapsed(e1, e2);
+        if (c->progress && ids.size() > 1)
+            fprintf(stderr, "[wsest] round %lld: configurations %zu..%zu of %zu done (%.1f ms evaluation)\n",
+                    (long long)c->last_rounds, i, j, ids.size(), elapsed(e0, e1));
         i = j;
     }
     return WSE_OK;

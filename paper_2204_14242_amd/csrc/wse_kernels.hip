@@ -79,15 +79,23 @@ __device__ __forceinline__ void wave_fence()
 
 // --------------------------------------------------------- hash-set inserts
 
+// slot of a key in a table of 2^log2cap slots (1 <= log2cap <= 32):
+// multiplicative (Fibonacci) hashing of the folded key, top bits
+__device__ __forceinline__ uint32_t slot_of(uint64_t key1, int log2cap)
+{
+    uint32_t x = (uint32_t)key1 ^ ((uint32_t)(key1 >> 32) * 0x85ebca6bu);
+    return (x * 0x9e3779b1u) >> (32 - log2cap);
+}
+
 // Insert into an open-addressing set (linear probing).  Entry layout
 // ((key + 1) << pb) | payload.  Returns 1 if a new key was placed, 0 if the
 // key was present (payload merged by `mode`), -1 if the table is full.
-template <bool LDS>
-__device__ __forceinline__ int set_insert(unsigned long long* slots, uint64_t mask, uint64_t entry,
-                                          int pb, int mode)
+__device__ __forceinline__ int set_insert(unsigned long long* slots, int log2cap, uint64_t entry, int pb,
+                                          int mode)
 {
-    uint64_t key1 = entry >> pb;
-    uint64_t pos = mix64(key1) & mask;
+    const uint64_t key1 = entry >> pb;
+    const uint32_t mask = (uint32_t)(((uint64_t)1 << log2cap) - 1);
+    uint32_t pos = slot_of(key1, log2cap);
     for (uint64_t probe = 0; probe <= mask; probe++) {
         unsigned long long old = atomicCAS(&slots[pos], 0ull, (unsigned long long)entry);
         if (old == 0) return 1;
@@ -105,10 +113,11 @@ __device__ __forceinline__ int set_insert(unsigned long long* slots, uint64_t ma
 }
 
 // position of key1 in a global table, -1 if absent
-__device__ __forceinline__ int64_t set_find(const unsigned long long* slots, uint64_t mask,
-                                            uint64_t key1, int pb)
+__device__ __forceinline__ int64_t set_find(const unsigned long long* slots, int log2cap, uint64_t key1,
+                                            int pb)
 {
-    uint64_t pos = mix64(key1) & mask;
+    const uint32_t mask = (uint32_t)(((uint64_t)1 << log2cap) - 1);
+    uint32_t pos = slot_of(key1, log2cap);
     for (uint64_t probe = 0; probe <= mask; probe++) {
         unsigned long long e = __hip_atomic_load(&slots[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (e == 0) return -1;
@@ -303,7 +312,6 @@ __device__ int64_t round_cap(int64_t bound, int* log2cap)
 {
     uint64_t want = (uint64_t)(bound > 32 ? bound : 32) * 2;
     int l = bits_for(want - 1);
-    if (l > 40) l = 40;
     *log2cap = l;
     return (int64_t)1 << l;
 }
@@ -463,6 +471,10 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t)
         int64_t bound = (int64_t)keys < ev[q] ? (int64_t)keys : ev[q];
         int l2 = 0;
         int64_t cap = round_cap(bound, &l2);
+        if (l2 > 32) {
+            bad = 2;
+            break;
+        }
         T.log2cap = l2;
         T.off = bytes;
         bytes += cap * 8;
@@ -479,7 +491,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t)
     }
     if (c.tag_bits > 31) bad = 1;
     if (bad) {
-        c.status = -3;
+        c.status = bad == 2 ? -2 : -3;
         bytes = 0;
     }
     c.table_bytes = bytes;
@@ -598,8 +610,7 @@ struct PassCtx {
     char* arena;
     unsigned long long* set0;
     unsigned long long* set1;
-    uint64_t lmask;
-    int lslots;
+    int lslots, llog;
     int fill0, fill1;
     uint64_t err;
 };
@@ -609,7 +620,6 @@ __device__ void flush_set(PassCtx& P, unsigned long long* set, int q, int mode, 
 {
     const TableDesc& T = P.c->tab[q];
     unsigned long long* slots = (unsigned long long*)(P.arena + T.off);
-    uint64_t mask = ((uint64_t)1 << T.log2cap) - 1;
     int lane = lane_id();
     bool overflow = false;
     for (int i = lane; i < P.lslots; i += kLanes) {
@@ -617,7 +627,7 @@ __device__ void flush_set(PassCtx& P, unsigned long long* set, int q, int mode, 
         if (e == 0) continue;
         set[i] = 0;
         if (!probe_wsec) {
-            if (set_insert<false>(slots, mask, e, T.pb, mode) < 0) overflow = true;
+            if (set_insert(slots, T.log2cap, e, T.pb, mode) < 0) overflow = true;
         } else {
             // layer sector with its block tag, probed in the wave sector table
             int tb = P.c->tag_bits;
@@ -625,7 +635,7 @@ __device__ void flush_set(PassCtx& P, unsigned long long* set, int q, int mode, 
             unsigned tag = (unsigned)(e & (((uint64_t)1 << tb) - 1));
             const TableDesc& W = P.c->tab[T_WSEC];
             const unsigned long long* ws = (const unsigned long long*)(P.arena + W.off);
-            int64_t pos = set_find(ws, ((uint64_t)1 << W.log2cap) - 1, key1, W.pb);
+            int64_t pos = set_find(ws, W.log2cap, key1, W.pb);
             if (pos >= 0) {
                 unsigned* tags = (unsigned*)(P.arena + W.tag_off);
                 atomicMax(&tags[pos], tag);
@@ -636,149 +646,210 @@ __device__ void flush_set(PassCtx& P, unsigned long long* set, int q, int mode, 
     wave_fence();
 }
 
-// insert one entry per valid lane into a per-wave LDS set; a lane whose left
-// neighbour holds the same entry skips (the set would merge it anyway)
-__device__ __forceinline__ int lds_add(PassCtx& P, unsigned long long* set, bool active,
-                                       uint64_t entry, int pb, int mode)
+// Insert one entry per lane (0 = nothing) into a per-wave LDS set.  A lane
+// whose left neighbour in its 16-lane row holds the same entry skips it; the
+// set merges the rest.  Returns the number of keys new to the set.
+__device__ __forceinline__ int lds_add(PassCtx& P, unsigned long long* set, uint64_t entry, int pb,
+                                       int mode)
 {
-    int lane = lane_id();
-    int64_t prev = shfl64((int64_t)entry, lane > 0 ? lane - 1 : 0);
-    int pact = __shfl((int)active, lane > 0 ? lane - 1 : 0);
-    bool lead = active && !(lane > 0 && pact && (uint64_t)prev == entry);
+    uint32_t lo = (uint32_t)entry, hi = (uint32_t)(entry >> 32);
+    // row_shr:1 (lane i reads lane i-1 of its row; row starts keep 0)
+    uint32_t plo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, 0x111, 0xf, 0xf, false);
+    uint32_t phi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, 0x111, 0xf, 0xf, false);
+    bool lead = entry != 0 && (plo != lo || phi != hi);
     int got = 0;
-    if (lead) got = set_insert<true>(set, P.lmask, entry, pb, mode);
+    if (lead) got = set_insert(set, P.llog, entry, pb, mode);
     return __popcll(__ballot(got == 1));
 }
+
+// constants of one instruction, one instruction per lane for a chunk of 64
+struct IConst {
+    int64_t S;       // lattice: align + elem * c0; affine: align + elem * c0
+    int64_t fs, fl;  // field * span + 1 of the pass's sector and line tables
+    int32_t st, elem;
+    int64_t kt[3], kb[3];  // affine: index coefficients of tid and bid
+};
+
+template <int KIND>
+__device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, const TableDesc& TS,
+                                              const TableDesc& TL)
+{
+    const Cfg& c = *P.c;
+    IConst r;
+    int f;
+    if (KIND == 0) {
+        const ExprL x = P.exl[e];
+        f = x.f;
+        r.st = x.st;
+        r.elem = c.elem ? c.elem : P.K->elem[f];
+        int64_t c0 = (int64_t)x.v[0] + c.sy * x.v[1] + c.sz * x.v[2];
+        r.S = P.K->align[f] + (int64_t)r.elem * c0;
+        for (int d = 0; d < 3; d++) {
+            r.kt[d] = 0;
+            r.kb[d] = 0;
+        }
+    } else {
+        const ExprA& x = P.exa[e];
+        f = x.f;
+        r.st = x.st;
+        r.elem = P.K->elem[f];
+        r.S = P.K->align[f] + (int64_t)r.elem * x.c0;
+        for (int d = 0; d < 3; d++) {
+            r.kt[d] = x.ct[d] + x.cg[d];
+            r.kb[d] = x.cb[d] + x.cg[d] * c.b[d];
+        }
+    }
+    r.fs = (int64_t)f * TS.span + 1;
+    r.fl = (int64_t)f * TL.span + 1;
+    return r;
+}
+
+__device__ __forceinline__ int32_t readlane32(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 template <int PASS, int KIND>
 __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, int64_t j1)
 {
     const Cfg& c = *P.c;
-    const KernelDev& K = *P.K;
-    const HwDev& H = *P.H;
     const int lane = lane_id();
+    // everything the loops read, loaded once into registers
+    const int log2_warp = P.H->log2_warp, log2_group = P.H->log2_group, log2_bank = P.H->log2_bank;
+    const int n_banks = P.H->l1_banks;
+    const int64_t pair_words = P.H->pair_words;
+    const int ls = P.H->log2_sector, ll = P.H->log2_line;
     const int spb = c.segs_per_block;
+    const int64_t nb0 = c.nb[0], nb1 = c.nb[1];
+    const int64_t b0 = c.b[0], b1 = c.b[1], b2 = c.b[2];
+    const int lb0 = c.lb[0], lb1 = c.lb[1];
+    const int64_t T0 = c.T[0], T1 = c.T[1], T2 = c.T[2];
+    const int64_t Pthr = c.P;
+    const int64_t sy = c.sy, sz = c.sz, g = c.g;
+    const int64_t f1 = c.fold[1], f2 = c.fold[2];
+    const int64_t smin = c.smin;
+    const int tag_bits = c.tag_bits;
     const int thr = P.lslots / 2 - kLanes;
     int64_t acc_up_ld = 0, acc_up_st = 0, acc_cyc = 0, acc_lanes = 0, acc_warps = 0;
-    const TableDesc& TS = c.tab[PASS == PASS_W ? T_WSEC : (PASS == PASS_B ? T_BSEC : T_WSEC)];
+    const TableDesc& TS = c.tab[PASS == PASS_B ? T_BSEC : T_WSEC];
     const TableDesc& TL = c.tab[PASS == PASS_W ? T_WLINE : (PASS == PASS_B ? T_BLINE : T_LLINE)];
-    const int ls = H.log2_sector, ll = H.log2_line;
-    const int sec_pb = PASS == PASS_W ? 2 : (PASS == PASS_L ? c.tag_bits : 0);
-    const int line_pb = PASS == PASS_L ? c.tag_bits : 0;
+    const int sec_pb = PASS == PASS_W ? 2 : (PASS == PASS_L ? tag_bits : 0);
+    const int line_pb = PASS == PASS_L ? tag_bits : 0;
     const int sec_mode = PASS == PASS_W ? MODE_OR : (PASS == PASS_L ? MODE_MAX : MODE_SET);
     const int line_mode = PASS == PASS_L ? MODE_MAX : MODE_SET;
     const bool do_sec = TS.log2cap > 0;
+    const int64_t umin_s = TS.umin, span_s = TS.span, umin_l = TL.umin, span_l = TL.span;
+    const int64_t uelem = c.uniform_elem;
+    const int E = c.E;
 
-    for (int64_t j = j0; j < j1; j++) {
-        int64_t k = k_lo + j / spb;
-        int64_t sgi = j % spb;
-        int64_t bid[3];
-        bid[0] = k % c.nb[0];
-        bid[1] = (k / c.nb[0]) % c.nb[1];
-        bid[2] = k / (c.nb[0] * c.nb[1]);
-        int64_t t = sgi * kLanes + lane;
-        bool inb = t < c.P;
-        int64_t tid[3];
-        tid[0] = t & (c.b[0] - 1);
-        tid[1] = (t >> c.lb[0]) & (c.b[1] - 1);
-        tid[2] = t >> (c.lb[0] + c.lb[1]);
-        int64_t gid[3];
-        for (int d = 0; d < 3; d++) gid[d] = bid[d] * c.b[d] + tid[d];
-        bool valid = inb && gid[0] < c.T[0] && gid[1] < c.T[1] && gid[2] < c.T[2];
-        uint64_t vmask = __ballot(valid);
-        acc_lanes += __popcll(vmask);
-        if (PASS == PASS_B) {
-            // modelled warps of this segment with a valid lane
-            int ws = 1 << H.log2_warp;
-            for (int w = 0; w < kLanes; w += ws) {
-                uint64_t m = ws >= 64 ? ~0ull : (((1ull << ws) - 1) << w);
-                if (vmask & m) acc_warps++;
-            }
-        }
-        if (vmask == 0) continue;
-        uint64_t tag = PASS == PASS_L ? (uint64_t)(k - c.smin + 1) : 0;
-        int64_t base = 0;
-        if (KIND == 0)
-            base = (gid[0] + c.g) + c.sy * (c.fold[1] * gid[1] + c.g) + c.sz * (c.fold[2] * gid[2] + c.g);
-        int64_t ubase = c.uniform_elem ? base * c.uniform_elem : 0;
+    for (int e0 = 0; e0 < E; e0 += kLanes) {
+        const int n_in = E - e0 < kLanes ? E - e0 : kLanes;
+        IConst ic;
+        if (e0 + lane < E) ic = load_iconst<KIND>(P, e0 + lane, TS, TL);
+        else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}};
+        const int32_t meta = ic.st | (ic.elem << 1);
 
-        for (int e = 0; e < c.E; e++) {
-            int f, st;
-            int64_t addr;
-            if (KIND == 0) {
-                const ExprL x = P.exl[e];
-                f = x.f;
-                st = x.st;
-                int64_t c0 = (int64_t)x.v[0] + c.sy * x.v[1] + c.sz * x.v[2];
-                if (c.uniform_elem) {
-                    addr = ubase + (K.align[f] + (int64_t)c.uniform_elem * c0);
-                } else {
-                    int64_t elem = c.elem ? c.elem : K.elem[f];
-                    addr = K.align[f] + elem * (base + c0);
+        // first segment of the item: block k, segment sgi, block coordinates
+        int64_t k = k_lo + j0 / spb;
+        int sgi = (int)(j0 % spb);
+        int64_t bx = k % nb0, by = (k / nb0) % nb1, bz = k / (nb0 * nb1);
+        for (int64_t j = j0; j < j1; j++) {
+            const int64_t t = (int64_t)sgi * kLanes + lane;
+            const bool inb = t < Pthr;
+            const int64_t tx = t & (b0 - 1), ty = (t >> lb0) & (b1 - 1), tz = t >> (lb0 + lb1);
+            const int64_t gx = bx * b0 + tx, gy = by * b1 + ty, gz = bz * b2 + tz;
+            const bool valid = inb && gx < T0 && gy < T1 && gz < T2;
+            const uint64_t vmask = __ballot(valid);
+            const int64_t kcur = k;
+            const int64_t bcur[3] = {bx, by, bz};
+            const int64_t tcur[3] = {tx, ty, tz};
+            // advance to the next segment
+            if (++sgi == spb) {
+                sgi = 0;
+                k++;
+                if (++bx == nb0) {
+                    bx = 0;
+                    if (++by == nb1) {
+                        by = 0;
+                        bz++;
+                    }
                 }
-            } else {
-                const ExprA& x = P.exa[e];
-                f = x.f;
-                st = x.st;
-                int64_t idx = x.c0;
-                for (int d = 0; d < 3; d++)
-                    idx += (x.ct[d] + x.cg[d]) * tid[d] + (x.cb[d] + x.cg[d] * c.b[d]) * bid[d];
-                addr = K.align[f] + (int64_t)K.elem[f] * idx;
             }
-            if (PASS == PASS_B && (P.fill0 > thr || P.fill1 > thr)) {
-                flush_set(P, P.set0, T_BSEC, MODE_SET, false);
-                flush_set(P, P.set1, T_BLINE, MODE_SET, false);
-                P.fill0 = P.fill1 = 0;
+            if (e0 == 0) {
+                acc_lanes += __popcll(vmask);
+                if (PASS == PASS_B) {
+                    const int ws = 1 << log2_warp;
+                    for (int w = 0; w < kLanes; w += ws) {
+                        uint64_t m = ws >= 64 ? ~0ull : (((1ull << ws) - 1) << w);
+                        if (vmask & m) acc_warps++;
+                    }
+                }
             }
-            if (PASS == PASS_W && (P.fill0 > thr || P.fill1 > thr)) {
-                flush_set(P, P.set0, T_WSEC, MODE_OR, false);
-                flush_set(P, P.set1, T_WLINE, MODE_SET, false);
-                P.fill0 = P.fill1 = 0;
-            }
-            if (PASS == PASS_L && (P.fill0 > thr || P.fill1 > thr)) {
-                flush_set(P, P.set0, T_WSEC, MODE_MAX, true);
-                flush_set(P, P.set1, T_LLINE, MODE_MAX, false);
-                P.fill0 = P.fill1 = 0;
-            }
-            int64_t sec = addr >> ls;
-            int64_t line = addr >> ll;
-            if (PASS == PASS_B) {
-                int64_t dcount = warp_distinct(valid, sec, H.log2_warp);
-                if (st) acc_up_st += dcount;
-                else acc_up_ld += dcount;
-                acc_cyc += group_cycles(valid, addr >> H.log2_bank, H.log2_group, H.l1_banks,
-                                        H.pair_words);
-                if (!st) {
-                    int64_t us = sec - TS.umin, ul = line - TL.umin;
-                    bool ok = (uint64_t)us < (uint64_t)TS.span && (uint64_t)ul < (uint64_t)TL.span;
+            if (vmask == 0) continue;
+            const uint64_t tag = PASS == PASS_L ? (uint64_t)(kcur - smin + 1) : 0;
+            int64_t base = 0;
+            if (KIND == 0) base = (gx + g) + sy * (f1 * gy + g) + sz * (f2 * gz + g);
+            const int64_t ubase = uelem ? base * uelem : 0;
+
+            for (int q = 0; q < n_in; q++) {
+                if (P.fill0 > thr || P.fill1 > thr) {
+                    if (PASS == PASS_B) {
+                        flush_set(P, P.set0, T_BSEC, MODE_SET, false);
+                        flush_set(P, P.set1, T_BLINE, MODE_SET, false);
+                    } else if (PASS == PASS_W) {
+                        flush_set(P, P.set0, T_WSEC, MODE_OR, false);
+                        flush_set(P, P.set1, T_WLINE, MODE_SET, false);
+                    } else {
+                        flush_set(P, P.set0, T_WSEC, MODE_MAX, true);
+                        flush_set(P, P.set1, T_LLINE, MODE_MAX, false);
+                    }
+                    P.fill0 = P.fill1 = 0;
+                }
+                const int64_t S = readlane64(ic.S, q);
+                const int32_t m = readlane32(meta, q);
+                const int st = m & 1;
+                int64_t addr;
+                if (KIND == 0) {
+                    addr = uelem ? ubase + S : base * (int64_t)(m >> 1) + S;
+                } else {
+                    int64_t idx = 0;
+                    for (int d = 0; d < 3; d++)
+                        idx += readlane64(ic.kt[d], q) * tcur[d] + readlane64(ic.kb[d], q) * bcur[d];
+                    addr = S + (int64_t)(m >> 1) * idx;
+                }
+                const int64_t sec = addr >> ls;
+                const int64_t line = addr >> ll;
+                const int64_t us = sec - umin_s, ul = line - umin_l;
+                if (PASS == PASS_B) {
+                    int64_t dcount = warp_distinct(valid, sec, log2_warp);
+                    if (st) acc_up_st += dcount;
+                    else acc_up_ld += dcount;
+                    acc_cyc += group_cycles(valid, addr >> log2_bank, log2_group, n_banks, pair_words);
+                    if (!st) {
+                        bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
+                        if (__ballot(valid && !ok)) P.err |= 1;
+                        bool act = valid && ok;
+                        uint64_t ks = act ? (uint64_t)(us + readlane64(ic.fs, q)) : 0;
+                        uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
+                        P.fill0 += lds_add(P, P.set0, ks, 0, MODE_SET);
+                        P.fill1 += lds_add(P, P.set1, kl, 0, MODE_SET);
+                    }
+                } else if (PASS == PASS_W) {
+                    if (st) acc_up_st += warp_distinct(valid, sec, log2_warp);
+                    bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
                     if (__ballot(valid && !ok)) P.err |= 1;
                     bool act = valid && ok;
-                    uint64_t ks = (uint64_t)((int64_t)f * TS.span + us + 1);
-                    uint64_t kl = (uint64_t)((int64_t)f * TL.span + ul + 1);
-                    P.fill0 += lds_add(P, P.set0, act, ks, 0, MODE_SET);
-                    P.fill1 += lds_add(P, P.set1, act, kl, 0, MODE_SET);
-                }
-            } else if (PASS == PASS_W) {
-                if (st) acc_up_st += warp_distinct(valid, sec, H.log2_warp);
-                int64_t us = sec - TS.umin, ul = line - TL.umin;
-                bool ok = (uint64_t)us < (uint64_t)TS.span && (uint64_t)ul < (uint64_t)TL.span;
-                if (__ballot(valid && !ok)) P.err |= 1;
-                bool act = valid && ok;
-                uint64_t ks = ((uint64_t)((int64_t)f * TS.span + us + 1) << 2) | (st ? 2u : 1u);
-                uint64_t kl = (uint64_t)((int64_t)f * TL.span + ul + 1);
-                P.fill0 += lds_add(P, P.set0, act, ks, sec_pb, sec_mode);
-                P.fill1 += lds_add(P, P.set1, act, kl, line_pb, line_mode);
-            } else {
-                int64_t ul = line - TL.umin;
-                bool ok = (uint64_t)ul < (uint64_t)TL.span;
-                if (__ballot(valid && !ok)) P.err |= 1;
-                uint64_t kl = ((uint64_t)((int64_t)f * TL.span + ul + 1) << line_pb) | tag;
-                P.fill1 += lds_add(P, P.set1, valid && ok, kl, line_pb, line_mode);
-                if (do_sec) {
-                    int64_t us = sec - TS.umin;
-                    bool in = (uint64_t)us < (uint64_t)TS.span;
-                    uint64_t ks = ((uint64_t)((int64_t)f * TS.span + us + 1) << sec_pb) | tag;
-                    P.fill0 += lds_add(P, P.set0, valid && in, ks, sec_pb, sec_mode);
+                    uint64_t ks = act ? (((uint64_t)(us + readlane64(ic.fs, q)) << 2) | (st ? 2u : 1u)) : 0;
+                    uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
+                    P.fill0 += lds_add(P, P.set0, ks, sec_pb, sec_mode);
+                    P.fill1 += lds_add(P, P.set1, kl, line_pb, line_mode);
+                } else {
+                    bool ok = (uint64_t)ul < (uint64_t)span_l;
+                    if (__ballot(valid && !ok)) P.err |= 1;
+                    uint64_t kl = (valid && ok) ? ((((uint64_t)(ul + readlane64(ic.fl, q))) << line_pb) | tag) : 0;
+                    P.fill1 += lds_add(P, P.set1, kl, line_pb, line_mode);
+                    if (do_sec) {
+                        bool in = valid && (uint64_t)us < (uint64_t)span_s;
+                        uint64_t ks = in ? ((((uint64_t)(us + readlane64(ic.fs, q))) << sec_pb) | tag) : 0;
+                        P.fill0 += lds_add(P, P.set0, ks, sec_pb, sec_mode);
+                    }
                 }
             }
         }
@@ -811,47 +882,55 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
     }
 }
 
-__global__ __launch_bounds__(256) void k_eval(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr,
-                                              const WorkEntry* work, int n_work, int64_t n_items,
-                                              char* arena, DevTables t, int lds_slots)
+__global__ __launch_bounds__(256) void k_eval(const Cfg* __restrict__ cfgs,
+                                              const int64_t* __restrict__ cfg_base,
+                                              Counters* __restrict__ ctr,
+                                              const WorkEntry* __restrict__ work, int n_work,
+                                              int64_t n_items, char* __restrict__ arena, DevTables t,
+                                              int lds_slots)
 {
     extern __shared__ unsigned long long lds[];
-    const int wave = (int)(threadIdx.x >> 6);
+    // the wave index is uniform across the wave; say so, so that everything
+    // derived from it (item, configuration) lives in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = lane_id();
     const int64_t n_waves = (int64_t)gridDim.x * kWavesPerGroup;
+    const int llog = 31 - __clz(lds_slots);
+    unsigned long long* set0 = lds + (size_t)wave * 2 * lds_slots;
     for (int64_t item = (int64_t)blockIdx.x * kWavesPerGroup + wave; item < n_items; item += n_waves) {
-    const WorkEntry* W = find_entry(work, n_work, item);
-    const Cfg& c = cfgs[W->cfg];
-    int64_t local = item - W->item_start;
-    int64_t j0 = local * W->per_item;
-    int64_t j1 = j0 + W->per_item < W->n_units ? j0 + W->per_item : W->n_units;
+        const WorkEntry* W = find_entry(work, n_work, item);
+        const int cfg = __builtin_amdgcn_readfirstlane(W->cfg);
+        const Cfg& c = cfgs[cfg];
+        const int64_t local = item - W->item_start;
+        const int64_t j0 = local * W->per_item;
+        const int64_t j1 = j0 + W->per_item < W->n_units ? j0 + W->per_item : W->n_units;
+        const int pass = __builtin_amdgcn_readfirstlane(W->what);
 
-    PassCtx P;
-    P.c = &c;
-    P.K = &t.kernels[c.kernel_id];
-    P.H = &t.hws[c.hw_id];
-    P.exl = c.kind == 0 ? t.expansions[c.expansion_id].ex : nullptr;
-    P.exa = c.kind == 1 ? (const ExprA*)P.K->items : nullptr;
-    P.arena = arena + cfg_base[W->cfg];
-    P.set0 = lds + (size_t)wave * 2 * lds_slots;
-    P.set1 = P.set0 + lds_slots;
-    P.lslots = lds_slots;
-    P.lmask = (uint64_t)lds_slots - 1;
-    P.fill0 = P.fill1 = 0;
-    P.err = 0;
-    for (int i = lane; i < 2 * lds_slots; i += kLanes) P.set0[i] = 0;
-    wave_fence();
-    Counters* cc = &ctr[W->cfg];
-    int pass = W->what;
-    if (c.kind == 0) {
-        if (pass == PASS_B) run_pass<PASS_B, 0>(P, cc, c.kB, j0, j1);
-        else if (pass == PASS_W) run_pass<PASS_W, 0>(P, cc, c.w0, j0, j1);
-        else run_pass<PASS_L, 0>(P, cc, c.smin, j0, j1);
-    } else {
-        if (pass == PASS_B) run_pass<PASS_B, 1>(P, cc, c.kB, j0, j1);
-        else if (pass == PASS_W) run_pass<PASS_W, 1>(P, cc, c.w0, j0, j1);
-        else run_pass<PASS_L, 1>(P, cc, c.smin, j0, j1);
-    }
+        PassCtx P;
+        P.c = &c;
+        P.K = &t.kernels[c.kernel_id];
+        P.H = &t.hws[c.hw_id];
+        P.exl = c.kind == 0 ? t.expansions[c.expansion_id].ex : nullptr;
+        P.exa = c.kind == 1 ? (const ExprA*)P.K->items : nullptr;
+        P.arena = arena + cfg_base[cfg];
+        P.set0 = set0;
+        P.set1 = set0 + lds_slots;
+        P.lslots = lds_slots;
+        P.llog = llog;
+        P.fill0 = P.fill1 = 0;
+        P.err = 0;
+        for (int i = lane; i < 2 * lds_slots; i += kLanes) P.set0[i] = 0;
+        wave_fence();
+        Counters* cc = &ctr[cfg];
+        if (c.kind == 0) {
+            if (pass == PASS_B) run_pass<PASS_B, 0>(P, cc, c.kB, j0, j1);
+            else if (pass == PASS_W) run_pass<PASS_W, 0>(P, cc, c.w0, j0, j1);
+            else run_pass<PASS_L, 0>(P, cc, c.smin, j0, j1);
+        } else {
+            if (pass == PASS_B) run_pass<PASS_B, 1>(P, cc, c.kB, j0, j1);
+            else if (pass == PASS_W) run_pass<PASS_W, 1>(P, cc, c.w0, j0, j1);
+            else run_pass<PASS_L, 1>(P, cc, c.smin, j0, j1);
+        }
     }
 }
 
