@@ -184,7 +184,8 @@ typedef struct {
 } wse_result;
 
 #define WSE_PLAIN 0    /* one launch sequence per configuration, host sync between */
-#define WSE_BATCHED 1  /* all configurations of all spaces in stage-wide launches */
+#define WSE_BATCHED 1  /* all configurations of all spaces in arena rounds; each round is one
+                          replay of a captured HIP graph of resident-loop kernels */
 
 /* Estimate every configuration of n_spaces spaces.  out[] receives the
  * results of space 0, then space 1, ...; rank_out[] (optional) the 0-based
@@ -194,6 +195,67 @@ typedef struct {
 wse_status wse_estimate(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces,
                         wse_result* out, int32_t* rank_out, int64_t out_capacity,
                         int32_t mode, void* stream);
+
+/* ----------------------------------------------------------------- tuning */
+
+/* Launch and table-sizing parameters of the evaluation kernels.  They
+ * change speed only: every result is identical under every tuning. */
+typedef struct {
+    int32_t lds_slots;          /* slots of each per-wave LDS hash set: 256, 512 or 1024 */
+    int32_t table_slack_log2;   /* HBM hash tables hold at least 2^slack slots per key bound (1..3) */
+    int64_t item_evals;         /* address evaluations per work item of a wave (2^12 .. 2^22) */
+    int32_t groups_per_cu;      /* resident-loop workgroups per compute unit (1 .. 64) */
+    int32_t pad;
+} wse_tuning;
+
+wse_status wse_get_tuning(wse_ctx* ctx, wse_tuning* tuning);
+wse_status wse_set_tuning(wse_ctx* ctx, const wse_tuning* tuning);
+/* Autotuner: estimate a seeded sample of about `sample` configurations of
+ * the given spaces under candidate tunings (coordinate descent over the
+ * four parameters), keep the fastest on this device, install it in the
+ * context and return it in *chosen. */
+wse_status wse_autotune(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces, int32_t sample,
+                        wse_tuning* chosen);
+
+/* ----------------------------------------------------------------- serving */
+
+/* A server estimates requests in the background with continuous batching:
+ * every admitted request is decoded on the device at once, and each arena
+ * round of the evaluation kernels packs the pending configurations of all
+ * admitted requests, oldest first, so that a request arriving while others
+ * run shares their rounds instead of waiting for them to finish.  Requests
+ * are admitted while the device memory of all requests in flight stays
+ * within memory_budget_bytes and at most max_inflight are in flight; the
+ * rest wait in a FIFO queue.  The results of a request do not depend on
+ * what else is in flight (every configuration owns its tables and
+ * counters). */
+typedef struct {
+    size_t memory_budget_bytes;  /* device memory for requests in flight (0 = 8 GiB) */
+    int32_t max_inflight;        /* requests in flight at once (0 = 64) */
+    int32_t max_queue;           /* queued requests before wse_submit says WSE_EBUSY (0 = 1000000) */
+} wse_server_opts;
+
+/* Start the server thread of a context (one per context). */
+wse_status wse_server_start(wse_ctx* ctx, const wse_server_opts* opts, wse_server** out);
+/* Queue a request: n_spaces spaces whose results (and optional ranks) are
+ * written to out/rank_out, host or device memory of out_capacity entries
+ * that must stay valid until the ticket completes.  The spaces are copied.
+ * Returns WSE_EBUSY when the queue is full and WSE_ENOMEM when the request
+ * alone exceeds the memory budget. */
+wse_status wse_submit(wse_server* srv, const wse_space* spaces, int32_t n_spaces, wse_result* out,
+                      int32_t* rank_out, int64_t out_capacity, uint64_t* ticket);
+/* *done = 1 once the request finished.  Returns WSE_ENOTREADY while it is
+ * queued or running, else the request's final status. */
+wse_status wse_poll(wse_server* srv, uint64_t ticket, int32_t* done);
+/* Wait up to timeout_us microseconds (< 0: no limit) for a request; returns
+ * its final status, or WSE_ENOTREADY on timeout. */
+wse_status wse_wait(wse_server* srv, uint64_t ticket, int64_t timeout_us);
+/* Steady-clock nanoseconds at which the request was submitted, admitted and
+ * finished (0 while not reached). */
+wse_status wse_ticket_times(wse_server* srv, uint64_t ticket, int64_t* submit_ns, int64_t* admit_ns,
+                            int64_t* done_ns);
+/* Finish every queued and running request, then stop and free the server. */
+wse_status wse_server_stop(wse_server* srv);
 
 /* Evaluate the hit-rate estimate R(O) of `fit` on the device for n values
  * O[i] (Sec. 4.5), with the same arithmetic the model uses.  O and R may be

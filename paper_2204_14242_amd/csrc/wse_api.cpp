@@ -1,16 +1,22 @@
 // Host side of the C-ABI: contexts, resident kernel/hardware tables, space
-// validation, arena planning and the launch sequence of the estimator.
-// All of the method's arithmetic runs in the kernels of wse_kernels.hip.
+// validation, requests ("jobs"), arena rounds, the synchronous estimate and
+// the continuous-batching server.  All of the method's arithmetic runs in
+// the kernels of wse_kernels.hip; the host validates, plans memory and
+// launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -27,12 +33,25 @@ static wse_status fail(wse_status s, const std::string& msg)
     return s;
 }
 
-#define HIP_TRY(expr)                                                                  \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
             return fail(WSE_EDEVICE, std::string(#expr " failed: ") + hipGetErrorString(e_)); \
     } while (0)
+
+#define WSE_TRY(expr)                \
+    do {                             \
+        wse_status s_ = (expr);      \
+        if (s_ != WSE_OK) return s_; \
+    } while (0)
+
+static int64_t now_ns()
+{
+    return (int64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
 
 namespace {
 
@@ -82,14 +101,104 @@ int ilog2(uint64_t v)
 
 bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+bool is_device_ptr(const void* p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (a && b) (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+}
+
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    hipEvent_t mark(hipStream_t st)
+    {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev.push_back(e);
+        }
+        hipEvent_t e = ev[used++];
+        (void)hipEventRecord(e, st);
+        return e;
+    }
+    void destroy()
+    {
+        for (auto e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        used = 0;
+    }
+};
+
+// one configuration space of a request, validated and copied
+struct SpaceHost {
+    SpaceDev dev;
+    std::vector<int32_t> shapes, outer;
+    std::vector<int64_t> expl;
+    int64_t total = 0;  // canonical size
+    int64_t n = 0;      // configurations estimated
+};
+
 }  // namespace
+
+// A request: its spaces, per-configuration device records and outputs.
+struct Job {
+    uint64_t ticket = 0;
+    std::vector<SpaceHost> sp;
+    int64_t total = 0;
+    wse_result* out = nullptr;
+    int32_t* rank_out = nullptr;
+    DevBuf<SpaceDev> d_spaces;
+    DevBuf<int32_t> d_shapes, d_outer, d_cfg_space, d_rank;
+    DevBuf<int64_t> d_explicit, d_space_first;
+    DevBuf<Cfg> d_cfgs;
+    DevBuf<Counters> d_ctr;
+    DevBuf<Result> d_res;
+    std::vector<Cfg> cfgs;          // host copy of the decoded configurations
+    std::vector<int64_t> runnable;  // configurations that go through the evaluation kernels
+    size_t next = 0;                // first runnable configuration not yet in a round
+    size_t mem_bytes = 0;
+    bool prepared = false, done = false;
+    wse_status status = WSE_OK;
+    std::string error;
+    int64_t t_submit = 0, t_admit = 0, t_done = 0;
+    void release()
+    {
+        d_spaces.release();
+        d_shapes.release();
+        d_outer.release();
+        d_cfg_space.release();
+        d_rank.release();
+        d_explicit.release();
+        d_space_first.release();
+        d_cfgs.release();
+        d_ctr.release();
+        d_res.release();
+        cfgs.clear();
+        cfgs.shrink_to_fit();
+        runnable.clear();
+        runnable.shrink_to_fit();
+    }
+};
 
 struct wse_ctx {
     int device = 0;
     char* arena = nullptr;
     size_t arena_bytes = 0;
     int n_cu = 256;
-    std::mutex mu;
+    std::mutex mu;      // execution resources: arena, expansions, graphs, round buffers
+    std::mutex reg_mu;  // the registries below; taken after mu, never before it
     std::vector<KernelHost> kernels;
     std::vector<HwDev> hws;
     std::vector<ExpansionHost> expansions;
@@ -97,27 +206,48 @@ struct wse_ctx {
     DevBuf<KernelDev> d_kernels;
     DevBuf<HwDev> d_hws;
     DevBuf<Expansion> d_exp;
-    // per-call scratch
-    DevBuf<SpaceDev> d_spaces;
-    DevBuf<int32_t> d_shapes, d_outer, d_cfg_space;
-    DevBuf<int64_t> d_explicit, d_base, d_space_first;
-    DevBuf<Cfg> d_cfgs;
-    DevBuf<Counters> d_ctr;
-    DevBuf<WorkEntry> d_work;
-    DevBuf<Result> d_res;
-    DevBuf<int32_t> d_rank;
     DevBuf<ExpandJob> d_jobs;
+    DevBuf<WorkEntry> d_work;
+    DevBuf<RoundDesc> d_rd;
+    hipStream_t rs = nullptr;  // stream of the round launches
+    // captured round graphs: [0] clear + evaluation launches, [1] counting
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    const void* graph_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int64_t graph_groups = 0;
+    int graph_lds = 0;
+    // tuning
     int lds_slots = 512;
+    int table_slack = 1;
+    int groups_per_cu = 16;
     int64_t target_evals = 1 << 17;
-    double timings[8] = {0};
     bool dirty_kernels = false, dirty_hws = false;
-    std::vector<hipEvent_t> events, round_events;
-    std::vector<int64_t> base;   // arena offset of each configuration's tables
-    // statistics of the last call
+    bool progress = false;  // WSE_PROGRESS=1: one stderr line per arena round
+    EventPool events, round_events;
+    // statistics of the last synchronous estimate
+    double timings[8] = {0};
     int64_t last_total = 0, last_table_bytes = 0, last_launches = 0, last_rounds = 0;
-    bool progress = false;   // WSE_PROGRESS=1: one stderr line per arena round
+    std::vector<Counters> last_ctr;
     std::vector<int32_t> last_E;
+    wse_server* server = nullptr;
 };
+
+struct wse_server {
+    wse_ctx* ctx = nullptr;
+    wse_server_opts opts;
+    std::thread th;
+    std::mutex m;
+    std::condition_variable cv;
+    std::deque<std::shared_ptr<Job>> queue;
+    std::vector<std::shared_ptr<Job>> active;
+    std::map<uint64_t, std::shared_ptr<Job>> all;
+    uint64_t next_ticket = 1;
+    size_t mem_in_flight = 0;
+    bool stopping = false;
+    hipStream_t stream = nullptr;
+};
+
+extern "C" wse_status wse_server_stop(wse_server* srv);
 
 extern "C" {
 
@@ -159,6 +289,12 @@ wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out)
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
     const char* pg = std::getenv("WSE_PROGRESS");
     c->progress = pg && pg[0] == '1';
+    e = hipStreamCreateWithFlags(&c->rs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipFree(c->arena);
+        delete c;
+        return fail(WSE_EDEVICE, std::string("round stream: ") + hipGetErrorString(e));
+    }
     *out = c;
     return WSE_OK;
 }
@@ -166,6 +302,7 @@ wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out)
 void wse_ctx_destroy(wse_ctx* c)
 {
     if (!c) return;
+    if (c->server) wse_server_stop(c->server);
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (auto& k : c->kernels) {
@@ -177,24 +314,19 @@ void wse_ctx_destroy(wse_ctx* c)
         (void)hipFree(x.d_out);
         (void)hipFree(x.d_keep);
     }
-    for (auto ev : c->events) (void)hipEventDestroy(ev);
-    for (auto ev : c->round_events) (void)hipEventDestroy(ev);
+    c->events.destroy();
+    c->round_events.destroy();
     c->d_kernels.release();
     c->d_hws.release();
     c->d_exp.release();
-    c->d_spaces.release();
-    c->d_shapes.release();
-    c->d_outer.release();
-    c->d_cfg_space.release();
-    c->d_explicit.release();
-    c->d_base.release();
-    c->d_space_first.release();
-    c->d_cfgs.release();
-    c->d_ctr.release();
-    c->d_work.release();
-    c->d_res.release();
-    c->d_rank.release();
     c->d_jobs.release();
+    c->d_work.release();
+    c->d_rd.release();
+    for (int g = 0; g < 2; g++) {
+        if (c->graph_exec[g]) (void)hipGraphExecDestroy(c->graph_exec[g]);
+        if (c->graph[g]) (void)hipGraphDestroy(c->graph[g]);
+    }
+    if (c->rs) (void)hipStreamDestroy(c->rs);
     (void)hipFree(c->arena);
     delete c;
 }
@@ -202,19 +334,20 @@ void wse_ctx_destroy(wse_ctx* c)
 wse_status wse_kernel_register(wse_ctx* c, const wse_kernel_desc* d, int32_t* kernel_id)
 {
     if (!c || !d || !kernel_id) return fail(WSE_EINVAL, "null argument");
-    std::lock_guard<std::mutex> lk(c->mu);
+    std::lock_guard<std::mutex> lk(c->reg_mu);
     if (d->kind != WSE_KERNEL_LATTICE && d->kind != WSE_KERNEL_AFFINE)
         return fail(WSE_EINVAL, "unknown kernel kind");
     if (d->n_fields < 1 || d->n_fields > 65535 || d->n_items < 1 || d->n_items > 65535 || !d->fields ||
         !d->items)
         return fail(WSE_EINVAL, "kernel needs 1..65535 fields and items");
-    if (d->ghost < 0) return fail(WSE_EINVAL, "negative ghost width");
+    if (d->ghost < 0 || d->ghost > (1 << 20)) return fail(WSE_EINVAL, "ghost width out of range");
     if (!(d->flops_per_lup >= 0.0)) return fail(WSE_EINVAL, "flops_per_lup must be >= 0");
     std::vector<int32_t> elem(d->n_fields);
     std::vector<int64_t> align(d->n_fields);
     int32_t uni = d->fields[0].elem_bytes;
     for (int f = 0; f < d->n_fields; f++) {
-        if (d->fields[f].elem_bytes <= 0) return fail(WSE_EINVAL, "field element size must be > 0");
+        if (d->fields[f].elem_bytes <= 0 || d->fields[f].elem_bytes > (1 << 20))
+            return fail(WSE_EINVAL, "field element size must be in 1..2^20");
         if (d->fields[f].align_bytes < -((int64_t)1 << 60) || d->fields[f].align_bytes > ((int64_t)1 << 60))
             return fail(WSE_ERANGE, "field alignment out of range");
         elem[f] = d->fields[f].elem_bytes;
@@ -290,7 +423,7 @@ wse_status wse_kernel_register(wse_ctx* c, const wse_kernel_desc* d, int32_t* ke
 wse_status wse_hw_register(wse_ctx* c, const wse_hw* h, int32_t* hw_id)
 {
     if (!c || !h || !hw_id) return fail(WSE_EINVAL, "null argument");
-    std::lock_guard<std::mutex> lk(c->mu);
+    std::lock_guard<std::mutex> lk(c->reg_mu);
     if (!pow2(h->line_bytes) || !pow2(h->sector_bytes) || h->sector_bytes > h->line_bytes)
         return fail(WSE_EINVAL, "line and sector sizes must be powers of two, sector <= line");
     if (!pow2(h->warp_size) || h->warp_size > 64) return fail(WSE_EINVAL, "warp size must be a power of two <= 64");
@@ -354,16 +487,7 @@ wse_status wse_last_timings(const wse_ctx* c, double* ms, int32_t n)
 
 // --------------------------------------------------------------- spaces
 
-namespace {
-
-struct SpaceHost {
-    SpaceDev dev;
-    std::vector<int32_t> shapes;
-    int64_t total = 0;   // canonical size
-    int64_t n = 0;       // configurations estimated
-};
-
-wse_status build_space(wse_ctx* c, const wse_space* s, SpaceHost& h)
+static wse_status build_space(wse_ctx* c, const wse_space* s, SpaceHost& h)
 {
     std::memset(&h.dev, 0, sizeof(h.dev));
     if (s->kernel_id < 0 || s->kernel_id >= (int)c->kernels.size()) return fail(WSE_EINVAL, "unknown kernel_id");
@@ -421,12 +545,15 @@ wse_status build_space(wse_ctx* c, const wse_space* s, SpaceHost& h)
     if (s->n_outer < 1 || !s->outer) return fail(WSE_EINVAL, "space needs at least one domain or grid");
     for (int i = 0; i < 3 * s->n_outer; i++)
         if (s->outer[i] < 1) return fail(WSE_EINVAL, "domain and grid extents must be >= 1");
+    h.outer.assign(s->outer, s->outer + 3 * (size_t)s->n_outer);
     h.dev.n_outer = s->n_outer;
     h.total = (int64_t)s->n_outer * h.dev.n_elem * h.dev.n_fz * h.dev.n_fy * h.dev.n_shapes;
     if (s->n_explicit < 0) return fail(WSE_EINVAL, "negative n_explicit");
+    h.expl.clear();
     if (s->n_explicit > 0) {
         if (!s->explicit_idx) return fail(WSE_EINVAL, "explicit_idx is null");
-        std::vector<int64_t> v(s->explicit_idx, s->explicit_idx + s->n_explicit);
+        h.expl.assign(s->explicit_idx, s->explicit_idx + s->n_explicit);
+        std::vector<int64_t> v(h.expl);
         for (int64_t x : v)
             if (x < 0 || x >= h.total) return fail(WSE_EINVAL, "explicit index outside the space");
         std::sort(v.begin(), v.end());
@@ -439,8 +566,9 @@ wse_status build_space(wse_ctx* c, const wse_space* s, SpaceHost& h)
     return WSE_OK;
 }
 
-wse_status sync_tables(wse_ctx* c, hipStream_t st)
+static wse_status sync_tables(wse_ctx* c, hipStream_t st)
 {
+    std::lock_guard<std::mutex> rk(c->reg_mu);
     if (c->dirty_kernels) {
         HIP_TRY(c->d_kernels.reserve(c->kernels.size()));
         std::vector<KernelDev> v;
@@ -458,21 +586,20 @@ wse_status sync_tables(wse_ctx* c, hipStream_t st)
     return WSE_OK;
 }
 
-DevTables dev_tables(wse_ctx* c, int n_spaces)
+static DevTables dev_tables(wse_ctx* c, const SpaceDev* spaces, int n_spaces)
 {
     DevTables t;
     t.kernels = c->d_kernels.p;
     t.hws = c->d_hws.p;
     t.expansions = c->d_exp.p;
-    t.spaces = c->d_spaces.p;
+    t.spaces = spaces;
     t.n_spaces = n_spaces;
     return t;
 }
 
 // make sure every (kernel, fy, fz) folding expansion a space needs is resident
-wse_status ensure_expansions(wse_ctx* c, std::vector<SpaceHost>& sp, hipStream_t st)
+static wse_status ensure_expansions(wse_ctx* c, std::vector<SpaceHost>& sp, hipStream_t st)
 {
-    std::vector<ExpandJob> jobs;
     size_t old_n = c->expansions.size();
     for (auto& h : sp) {
         if (h.dev.kind != WSE_KERNEL_LATTICE) continue;
@@ -486,7 +613,12 @@ wse_status ensure_expansions(wse_ctx* c, std::vector<SpaceHost>& sp, hipStream_t
                     x.fy = h.dev.fy[i];
                     x.fz = h.dev.fz[j];
                     x.index = (int)c->expansions.size();
-                    size_t n = (size_t)c->kernels[x.kernel_id].dev.n_items * x.fy * x.fz;
+                    size_t n_items;
+                    {
+                        std::lock_guard<std::mutex> rk(c->reg_mu);
+                        n_items = (size_t)c->kernels[x.kernel_id].dev.n_items;
+                    }
+                    size_t n = n_items * x.fy * x.fz;
                     HIP_TRY(hipMalloc((void**)&x.d_out, n * sizeof(ExprL)));
                     HIP_TRY(hipMalloc((void**)&x.d_keep, n * sizeof(int32_t)));
                     c->expansions.push_back(x);
@@ -514,6 +646,7 @@ wse_status ensure_expansions(wse_ctx* c, std::vector<SpaceHost>& sp, hipStream_t
     HIP_TRY(hipStreamSynchronize(st));
     c->d_exp.release();
     c->d_exp = nb;
+    std::vector<ExpandJob> jobs;
     for (size_t i = old_n; i < c->expansions.size(); i++) {
         ExpandJob j;
         j.kernel_id = c->expansions[i].kernel_id;
@@ -527,141 +660,279 @@ wse_status ensure_expansions(wse_ctx* c, std::vector<SpaceHost>& sp, hipStream_t
     }
     HIP_TRY(c->d_jobs.reserve(jobs.size()));
     HIP_TRY(hipMemcpyAsync(c->d_jobs.p, jobs.data(), jobs.size() * sizeof(ExpandJob), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_expand(c->d_jobs.p, (int)jobs.size(), dev_tables(c, 0), st));
+    HIP_TRY(launch_expand(c->d_jobs.p, (int)jobs.size(), dev_tables(c, nullptr, 0), st));
     HIP_TRY(hipStreamSynchronize(st));
     return WSE_OK;
 }
 
-bool is_device_ptr(const void* p)
+// ------------------------------------------------------------------ jobs
+
+static wse_status job_init(wse_ctx* c, Job& j, const wse_space* spaces, int32_t n_spaces)
 {
-    hipPointerAttribute_t a;
-    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
+    std::lock_guard<std::mutex> rk(c->reg_mu);
+    j.sp.assign(n_spaces, SpaceHost());
+    j.total = 0;
+    for (int i = 0; i < n_spaces; i++) {
+        wse_status s = build_space(c, &spaces[i], j.sp[i]);
+        if (s != WSE_OK) return fail(s, "space " + std::to_string(i) + ": " + g_err);
+        j.sp[i].dev.first = j.total;
+        j.sp[i].dev.n_configs = j.sp[i].n;
+        j.total += j.sp[i].n;
     }
-    return a.type == hipMemoryTypeDevice;
+    if (j.total > ((int64_t)1 << 31)) return fail(WSE_EINVAL, "too many configurations in one request");
+    size_t per = sizeof(Cfg) + sizeof(Counters) + sizeof(Result) + 2 * sizeof(int32_t);
+    j.mem_bytes = (size_t)j.total * per + 4096 * (size_t)(n_spaces + 1);
+    for (auto& h : j.sp)
+        j.mem_bytes += (h.shapes.size() + h.outer.size()) * 4 + h.expl.size() * 8 + sizeof(SpaceDev);
+    return WSE_OK;
 }
 
-struct Timer {
-    hipStream_t st;
-    std::vector<hipEvent_t>* pool;
-    size_t used = 0;
-    hipEvent_t mark()
-    {
-        if (used == pool->size()) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
-            pool->push_back(e);
-        }
-        hipEvent_t e = (*pool)[used++];
-        (void)hipEventRecord(e, st);
-        return e;
+// upload the spaces, decode every configuration on the device, read the plan back
+static wse_status job_prepare(wse_ctx* c, Job& j, hipStream_t st)
+{
+    WSE_TRY(sync_tables(c, st));
+    WSE_TRY(ensure_expansions(c, j.sp, st));
+    const int n_spaces = (int)j.sp.size();
+    std::vector<int32_t> shapes, outer;
+    std::vector<int64_t> expl;
+    std::vector<size_t> shape_off(n_spaces), outer_off(n_spaces), expl_off(n_spaces);
+    for (int i = 0; i < n_spaces; i++) {
+        shape_off[i] = shapes.size();
+        shapes.insert(shapes.end(), j.sp[i].shapes.begin(), j.sp[i].shapes.end());
+        outer_off[i] = outer.size();
+        outer.insert(outer.end(), j.sp[i].outer.begin(), j.sp[i].outer.end());
+        expl_off[i] = expl.size();
+        expl.insert(expl.end(), j.sp[i].expl.begin(), j.sp[i].expl.end());
     }
+    HIP_TRY(j.d_shapes.reserve(std::max<size_t>(shapes.size(), 1)));
+    HIP_TRY(j.d_outer.reserve(std::max<size_t>(outer.size(), 1)));
+    HIP_TRY(j.d_explicit.reserve(std::max<size_t>(expl.size(), 1)));
+    HIP_TRY(j.d_spaces.reserve(n_spaces));
+    std::vector<SpaceDev> sdev(n_spaces);
+    std::vector<int64_t> first(n_spaces + 1);
+    std::vector<int32_t> cfg_space(j.total);
+    for (int i = 0; i < n_spaces; i++) {
+        sdev[i] = j.sp[i].dev;
+        sdev[i].shapes = j.d_shapes.p + shape_off[i];
+        sdev[i].outer = j.d_outer.p + outer_off[i];
+        sdev[i].explicit_idx = j.sp[i].expl.empty() ? nullptr : j.d_explicit.p + expl_off[i];
+        first[i] = j.sp[i].dev.first;
+        for (int64_t q = 0; q < j.sp[i].n; q++) cfg_space[j.sp[i].dev.first + q] = i;
+    }
+    first[n_spaces] = j.total;
+    HIP_TRY(hipMemcpyAsync(j.d_shapes.p, shapes.data(), shapes.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(j.d_outer.p, outer.data(), outer.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (!expl.empty())
+        HIP_TRY(hipMemcpyAsync(j.d_explicit.p, expl.data(), expl.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(j.d_spaces.p, sdev.data(), n_spaces * sizeof(SpaceDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(j.d_cfgs.reserve(j.total));
+    HIP_TRY(j.d_ctr.reserve(j.total));
+    HIP_TRY(j.d_res.reserve(j.total));
+    HIP_TRY(j.d_rank.reserve(j.total));
+    HIP_TRY(j.d_cfg_space.reserve(j.total));
+    HIP_TRY(j.d_space_first.reserve(n_spaces + 1));
+    HIP_TRY(hipMemcpyAsync(j.d_space_first.p, first.data(), first.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(j.d_cfg_space.p, cfg_space.data(), j.total * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_decode(j.d_cfgs.p, j.total, dev_tables(c, j.d_spaces.p, n_spaces), c->table_slack, st));
+    HIP_TRY(launch_fill_zero(j.d_ctr.p, j.total * (int64_t)sizeof(Counters), st));
+    j.cfgs.resize(j.total);
+    HIP_TRY(hipMemcpyAsync(j.cfgs.data(), j.d_cfgs.p, j.total * sizeof(Cfg), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // configurations whose tables exceed the whole arena cannot run
+    bool patched = false;
+    j.runnable.clear();
+    for (int64_t i = 0; i < j.total; i++) {
+        if (j.cfgs[i].status != 0) continue;
+        if (j.cfgs[i].table_bytes > (int64_t)c->arena_bytes) {
+            j.cfgs[i].status = WSE_ENOMEM;
+            HIP_TRY(hipMemcpyAsync(&j.d_cfgs.p[i].status, &j.cfgs[i].status, sizeof(int32_t),
+                                   hipMemcpyHostToDevice, st));
+            patched = true;
+            continue;
+        }
+        j.runnable.push_back(i);
+    }
+    if (patched) HIP_TRY(hipStreamSynchronize(st));
+    j.next = 0;
+    j.prepared = true;
+    return WSE_OK;
+}
+
+// model, ranks and copy-out of a request whose configurations all ran
+static wse_status job_finish(wse_ctx* c, Job& j, hipStream_t st)
+{
+    const int n_spaces = (int)j.sp.size();
+    DevTables t = dev_tables(c, j.d_spaces.p, n_spaces);
+    bool out_dev = is_device_ptr(j.out);
+    Result* res = out_dev ? (Result*)j.out : j.d_res.p;
+    HIP_TRY(launch_reduce(j.d_cfgs.p, j.d_ctr.p, j.total, t, res, st));
+    if (j.rank_out) {
+        bool rank_dev = is_device_ptr(j.rank_out);
+        int32_t* rk = rank_dev ? j.rank_out : j.d_rank.p;
+        HIP_TRY(launch_rank(res, j.d_space_first.p, j.d_cfg_space.p, j.total, rk, st));
+        if (!rank_dev) HIP_TRY(hipMemcpyAsync(j.rank_out, rk, j.total * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    }
+    if (!out_dev) HIP_TRY(hipMemcpyAsync(j.out, res, j.total * sizeof(Result), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return WSE_OK;
+}
+
+struct RoundItem {
+    Job* job;
+    int64_t id;
 };
 
-float elapsed(hipEvent_t a, hipEvent_t b)
+// Take the next configurations of the given requests, oldest request first,
+// while their tables fit the arena together (continuous batching: one round
+// may finish one request and start the next); at most `limit` of them.
+static void form_round(wse_ctx* c, const std::vector<Job*>& jobs, std::vector<RoundItem>& round, size_t limit)
 {
-    float ms = 0.f;
-    if (a && b) (void)hipEventElapsedTime(&ms, a, b);
-    return ms;
+    round.clear();
+    int64_t used = 0;
+    for (Job* j : jobs) {
+        while (j->next < j->runnable.size() && round.size() < limit) {
+            int64_t id = j->runnable[j->next];
+            int64_t b = j->cfgs[id].table_bytes;
+            if (!round.empty() && used + b > (int64_t)c->arena_bytes) return;
+            used += b;
+            round.push_back({j, id});
+            j->next++;
+        }
+        if (round.size() >= limit) return;
+    }
 }
 
-}  // namespace
-
-extern "C" wse_status wse_space_size(wse_ctx* c, const wse_space* s, int64_t* n)
+// (Re)capture the round graphs when anything their kernel arguments name
+// has changed: the work list buffer, the resident tables, the tuning.
+static wse_status ensure_round_graphs(wse_ctx* c, int64_t groups)
 {
-    if (!c || !s || !n) return fail(WSE_EINVAL, "null argument");
-    std::lock_guard<std::mutex> lk(c->mu);
-    SpaceHost h;
-    wse_status st = build_space(c, s, h);
-    if (st != WSE_OK) return st;
-    *n = h.n;
+    DevTables t = dev_tables(c, nullptr, 0);
+    const void* key[6] = {c->d_work.p, c->d_rd.p, t.kernels, t.hws, t.expansions, c->arena};
+    bool same = c->graph_exec[0] && c->graph_groups == groups && c->graph_lds == c->lds_slots;
+    for (int i = 0; i < 6 && same; i++) same = key[i] == c->graph_key[i];
+    if (same) return WSE_OK;
+    for (int g = 0; g < 2; g++) {
+        if (c->graph_exec[g]) (void)hipGraphExecDestroy(c->graph_exec[g]);
+        if (c->graph[g]) (void)hipGraphDestroy(c->graph[g]);
+        c->graph_exec[g] = nullptr;
+        c->graph[g] = nullptr;
+    }
+    // graph 0: clear the round's tables, evaluate block+wave, evaluate layers
+    HIP_TRY(hipStreamBeginCapture(c->rs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_round_fill(c->arena, c->d_rd.p, groups, c->rs);
+    if (e == hipSuccess) e = launch_eval(c->d_work.p, c->d_rd.p, 0, t, c->lds_slots, groups, c->rs);
+    if (e == hipSuccess) e = launch_eval(c->d_work.p, c->d_rd.p, 1, t, c->lds_slots, groups, c->rs);
+    hipError_t e2 = hipStreamEndCapture(c->rs, &c->graph[0]);
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(WSE_EDEVICE, std::string("round graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    // graph 1: count the round's tables
+    HIP_TRY(hipStreamBeginCapture(c->rs, hipStreamCaptureModeThreadLocal));
+    e = launch_count(c->d_work.p, c->d_rd.p, groups, c->rs);
+    e2 = hipStreamEndCapture(c->rs, &c->graph[1]);
+    if (e != hipSuccess || e2 != hipSuccess)
+        return fail(WSE_EDEVICE, std::string("count graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    for (int g = 0; g < 2; g++) HIP_TRY(hipGraphInstantiate(&c->graph_exec[g], c->graph[g], nullptr, nullptr, 0));
+    for (int i = 0; i < 6; i++) c->graph_key[i] = key[i];
+    c->graph_groups = groups;
+    c->graph_lds = c->lds_slots;
+    return WSE_OK;
+}
+
+// Evaluation and counting launches of one round; all tables of the round
+// live in the arena at once.  Batched rounds replay the captured graphs;
+// plain rounds launch the same kernels one by one.
+static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hipStream_t st, bool use_graph,
+                            float* eval_ms, float* count_ms)
+{
+    std::vector<WorkEntry> all;
+    int64_t items[3] = {0, 0, 0}, used = 0;
+    int32_t counts[3] = {0, 0, 0};
+    std::vector<WorkEntry> lists[3];
+    for (const RoundItem& r : round) {
+        const Cfg& g = r.job->cfgs[r.id];
+        int64_t base = used;
+        used += g.table_bytes;
+        int64_t spb = g.segs_per_block;
+        int64_t per = std::max<int64_t>(1, c->target_evals / ((int64_t)kLanes * std::max(1, g.E)));
+        auto add = [&](int which, int what, int64_t units, int64_t per_item) {
+            if (units <= 0) return;
+            WorkEntry e;
+            e.cfg = r.job->d_cfgs.p + r.id;
+            e.ctr = r.job->d_ctr.p + r.id;
+            e.tables = c->arena + base;
+            e.what = what;
+            e.pad = 0;
+            e.n_units = units;
+            e.per_item = per_item;
+            e.item_start = items[which];
+            items[which] += (units + per_item - 1) / per_item;
+            lists[which].push_back(e);
+        };
+        add(0, PASS_B, spb, per);
+        add(0, PASS_W, (g.w1 - g.w0) * spb, per);
+        if (g.smin >= 0) add(1, PASS_L, (g.w0 - g.smin) * spb, per);
+        for (int t = 0; t < N_TABLES; t++)
+            if (g.tab[t].log2cap > 0) add(2, t, (int64_t)1 << g.tab[t].log2cap, 1 << 16);
+    }
+    RoundDesc rd;
+    std::memset(&rd, 0, sizeof(rd));
+    rd.fill_bytes = used;
+    for (int w = 0; w < 3; w++) {
+        rd.items[w] = items[w];
+        rd.first[w] = (int32_t)all.size();
+        rd.n_work[w] = counts[w] = (int32_t)lists[w].size();
+        all.insert(all.end(), lists[w].begin(), lists[w].end());
+    }
+    c->last_table_bytes += used;
+    HIP_TRY(c->d_work.reserve(std::max<size_t>(all.size(), 1)));
+    HIP_TRY(c->d_rd.reserve(1));
+    const int64_t groups = (int64_t)c->n_cu * c->groups_per_cu;
+    if (use_graph) WSE_TRY(ensure_round_graphs(c, groups));
+    // the round runs on the round stream after everything queued on st
+    c->round_events.used = 0;
+    hipEvent_t dep = c->round_events.mark(st);
+    HIP_TRY(hipStreamWaitEvent(c->rs, dep, 0));
+    if (!all.empty())
+        HIP_TRY(hipMemcpyAsync(c->d_work.p, all.data(), all.size() * sizeof(WorkEntry), hipMemcpyHostToDevice, c->rs));
+    HIP_TRY(hipMemcpyAsync(c->d_rd.p, &rd, sizeof(rd), hipMemcpyHostToDevice, c->rs));
+    hipEvent_t e0 = c->round_events.mark(c->rs);
+    if (use_graph) {
+        HIP_TRY(hipGraphLaunch(c->graph_exec[0], c->rs));
+    } else {
+        DevTables t = dev_tables(c, nullptr, 0);
+        HIP_TRY(launch_round_fill(c->arena, c->d_rd.p, groups, c->rs));
+        if (counts[0]) HIP_TRY(launch_eval(c->d_work.p, c->d_rd.p, 0, t, c->lds_slots, groups, c->rs));
+        if (counts[1]) HIP_TRY(launch_eval(c->d_work.p, c->d_rd.p, 1, t, c->lds_slots, groups, c->rs));
+    }
+    hipEvent_t e1 = c->round_events.mark(c->rs);
+    if (use_graph) {
+        HIP_TRY(hipGraphLaunch(c->graph_exec[1], c->rs));
+    } else if (counts[2]) {
+        HIP_TRY(launch_count(c->d_work.p, c->d_rd.p, groups, c->rs));
+    }
+    hipEvent_t e2 = c->round_events.mark(c->rs);
+    // the host reuses the work list, the round descriptor and the arena next round
+    HIP_TRY(hipStreamSynchronize(c->rs));
+    c->last_rounds++;
+    c->last_launches += use_graph ? 2 : (counts[0] ? 1 : 0) + (counts[1] ? 1 : 0);
+    float ev = elapsed(e0, e1);
+    *eval_ms += ev;
+    *count_ms += elapsed(e1, e2);
+    if (c->progress)
+        fprintf(stderr, "[wsest] round %lld: %zu configurations, %.1f ms evaluation\n", (long long)c->last_rounds,
+                round.size(), ev);
     return WSE_OK;
 }
 
 // ------------------------------------------------------------- estimate
 
-// Run the evaluation and counting launches of the configurations `ids`, in
-// rounds whose hash tables fit the arena together.
-static wse_status run_rounds(wse_ctx* c, const std::vector<Cfg>& cfgs, const std::vector<int64_t>& ids,
-                             hipStream_t st, float* eval_ms, float* count_ms)
+extern "C" wse_status wse_space_size(wse_ctx* c, const wse_space* s, int64_t* n)
 {
-    std::vector<int64_t>& base = c->base;
-    size_t i = 0;
-    while (i < ids.size()) {
-        int64_t used = 0;
-        size_t j = i;
-        while (j < ids.size()) {
-            int64_t b = cfgs[ids[j]].table_bytes;
-            if (j > i && used + b > (int64_t)c->arena_bytes) break;
-            base[ids[j]] = used;
-            used += b;
-            j++;
-        }
-        // one round: configurations ids[i..j)
-        std::vector<WorkEntry> work_a, work_b, work_c;
-        int64_t items_a = 0, items_b = 0, items_c = 0;
-        for (size_t q = i; q < j; q++) {
-            const Cfg& g = cfgs[ids[q]];
-            int64_t spb = g.segs_per_block;
-            int64_t per = std::max<int64_t>(1, c->target_evals / ((int64_t)kLanes * std::max(1, g.E)));
-            auto add = [&](std::vector<WorkEntry>& w, int64_t& items, int what, int64_t units, int64_t per_item) {
-                if (units <= 0) return;
-                WorkEntry e;
-                e.cfg = (int32_t)ids[q];
-                e.what = what;
-                e.n_units = units;
-                e.per_item = per_item;
-                e.item_start = items;
-                items += (units + per_item - 1) / per_item;
-                w.push_back(e);
-            };
-            add(work_a, items_a, PASS_B, spb, per);
-            add(work_a, items_a, PASS_W, (g.w1 - g.w0) * spb, per);
-            if (g.smin >= 0) add(work_b, items_b, PASS_L, (g.w0 - g.smin) * spb, per);
-            c->last_table_bytes += g.table_bytes;
-            for (int t = 0; t < N_TABLES; t++)
-                if (g.tab[t].log2cap > 0) add(work_c, items_c, t, (int64_t)1 << g.tab[t].log2cap, 1 << 16);
-        }
-        if (j - i == 1)
-            HIP_TRY(hipMemcpyAsync(c->d_base.p + ids[i], &base[ids[i]], sizeof(int64_t), hipMemcpyHostToDevice, st));
-        else
-            HIP_TRY(hipMemcpyAsync(c->d_base.p, base.data(), base.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        HIP_TRY(launch_fill_zero(c->arena, used, st));
-        size_t nw = work_a.size() + work_b.size() + work_c.size();
-        HIP_TRY(c->d_work.reserve(nw));
-        std::vector<WorkEntry> all;
-        all.insert(all.end(), work_a.begin(), work_a.end());
-        all.insert(all.end(), work_b.begin(), work_b.end());
-        all.insert(all.end(), work_c.begin(), work_c.end());
-        if (!all.empty())
-            HIP_TRY(hipMemcpyAsync(c->d_work.p, all.data(), all.size() * sizeof(WorkEntry), hipMemcpyHostToDevice, st));
-        DevTables t = dev_tables(c, 0);
-        int64_t max_groups = (int64_t)c->n_cu * 16;
-        Timer tm{st, &c->round_events};
-        hipEvent_t e0 = tm.mark();
-        c->last_rounds++;
-        c->last_launches += (work_a.empty() ? 0 : 1) + (work_b.empty() ? 0 : 1);
-        if (!work_a.empty())
-            HIP_TRY(launch_eval(c->d_cfgs.p, c->d_base.p, c->d_ctr.p, c->d_work.p, (int)work_a.size(), items_a,
-                                c->arena, t, c->lds_slots, max_groups, st));
-        if (!work_b.empty())
-            HIP_TRY(launch_eval(c->d_cfgs.p, c->d_base.p, c->d_ctr.p, c->d_work.p + work_a.size(),
-                                (int)work_b.size(), items_b, c->arena, t, c->lds_slots, max_groups, st));
-        hipEvent_t e1 = tm.mark();
-        if (!work_c.empty())
-            HIP_TRY(launch_count(c->d_cfgs.p, c->d_base.p, c->d_ctr.p, c->d_work.p + work_a.size() + work_b.size(),
-                                 (int)work_c.size(), items_c, c->arena, max_groups, st));
-        hipEvent_t e2 = tm.mark();
-        // the host reuses its work lists and base offsets next round
-        HIP_TRY(hipStreamSynchronize(st));
-        *eval_ms += elapsed(e0, e1);
-        *count_ms += elapsed(e1, e2);
-        if (c->progress && ids.size() > 1)
-            fprintf(stderr, "[wsest] round %lld: configurations %zu..%zu of %zu done (%.1f ms evaluation)\n",
-                    (long long)c->last_rounds, i, j, ids.size(), elapsed(e0, e1));
-        i = j;
-    }
+    if (!c || !s || !n) return fail(WSE_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(c->reg_mu);
+    SpaceHost h;
+    WSE_TRY(build_space(c, s, h));
+    *n = h.n;
     return WSE_OK;
 }
 
@@ -673,136 +944,78 @@ extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t 
     std::lock_guard<std::mutex> lk(c->mu);
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
-    std::vector<SpaceHost> sp(n_spaces);
-    int64_t total = 0;
-    for (int i = 0; i < n_spaces; i++) {
-        wse_status s = build_space(c, &spaces[i], sp[i]);
-        if (s != WSE_OK) return fail(s, "space " + std::to_string(i) + ": " + g_err);
-        sp[i].dev.first = total;
-        sp[i].dev.n_configs = sp[i].n;
-        total += sp[i].n;
-    }
-    if (total > out_capacity) return fail(WSE_EINVAL, "out_capacity is smaller than the number of configurations");
-    if (!out && total > 0) return fail(WSE_EINVAL, "out is null");
-    if (total == 0) return WSE_OK;
-    if (total > ((int64_t)1 << 31)) return fail(WSE_EINVAL, "too many configurations in one call");
-    wse_status s = sync_tables(c, st);
-    if (s != WSE_OK) return s;
-    s = ensure_expansions(c, sp, st);
-    if (s != WSE_OK) return s;
-
-    // space tables on the device
-    std::vector<int32_t> shapes, outer;
-    std::vector<int64_t> expl;
-    std::vector<size_t> shape_off(n_spaces), outer_off(n_spaces), expl_off(n_spaces);
-    for (int i = 0; i < n_spaces; i++) {
-        shape_off[i] = shapes.size();
-        shapes.insert(shapes.end(), sp[i].shapes.begin(), sp[i].shapes.end());
-        outer_off[i] = outer.size();
-        outer.insert(outer.end(), spaces[i].outer, spaces[i].outer + 3 * spaces[i].n_outer);
-        expl_off[i] = expl.size();
-        if (spaces[i].n_explicit > 0)
-            expl.insert(expl.end(), spaces[i].explicit_idx, spaces[i].explicit_idx + spaces[i].n_explicit);
-    }
-    HIP_TRY(c->d_shapes.reserve(shapes.size()));
-    HIP_TRY(c->d_outer.reserve(outer.size()));
-    HIP_TRY(c->d_explicit.reserve(std::max<size_t>(expl.size(), 1)));
-    HIP_TRY(c->d_spaces.reserve(n_spaces));
-    std::vector<SpaceDev> sdev(n_spaces);
-    for (int i = 0; i < n_spaces; i++) {
-        sdev[i] = sp[i].dev;
-        sdev[i].shapes = c->d_shapes.p + shape_off[i];
-        sdev[i].outer = c->d_outer.p + outer_off[i];
-        sdev[i].explicit_idx = spaces[i].n_explicit > 0 ? c->d_explicit.p + expl_off[i] : nullptr;
-    }
-    HIP_TRY(hipMemcpyAsync(c->d_shapes.p, shapes.data(), shapes.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(c->d_outer.p, outer.data(), outer.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    if (!expl.empty())
-        HIP_TRY(hipMemcpyAsync(c->d_explicit.p, expl.data(), expl.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(c->d_spaces.p, sdev.data(), n_spaces * sizeof(SpaceDev), hipMemcpyHostToDevice, st));
-
-    HIP_TRY(c->d_cfgs.reserve(total));
-    HIP_TRY(c->d_ctr.reserve(total));
-    HIP_TRY(c->d_res.reserve(total));
-    HIP_TRY(c->d_rank.reserve(total));
-    HIP_TRY(c->d_base.reserve(total));
-    HIP_TRY(c->d_cfg_space.reserve(total));
-    HIP_TRY(c->d_space_first.reserve(n_spaces + 1));
-    Timer tm{st, &c->events};
-    hipEvent_t t0 = tm.mark();
-    DevTables t = dev_tables(c, n_spaces);
-    HIP_TRY(launch_decode(c->d_cfgs.p, total, t, c->lds_slots, st));
-    HIP_TRY(launch_fill_zero(c->d_ctr.p, total * (int64_t)sizeof(Counters), st));
-    std::vector<Cfg> cfgs(total);
-    HIP_TRY(hipMemcpyAsync(cfgs.data(), c->d_cfgs.p, total * sizeof(Cfg), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    hipEvent_t t1 = tm.mark();
-
-    // configurations whose tables exceed the arena cannot run
-    std::vector<int64_t> ids;
-    bool patched = false;
-    for (int64_t i = 0; i < total; i++) {
-        if (cfgs[i].status != 0) continue;
-        if (cfgs[i].table_bytes > (int64_t)c->arena_bytes) {
-            cfgs[i].status = WSE_ENOMEM;
-            patched = true;
-            continue;
-        }
-        ids.push_back(i);
-    }
-    if (patched)
-        HIP_TRY(hipMemcpyAsync(c->d_cfgs.p, cfgs.data(), total * sizeof(Cfg), hipMemcpyHostToDevice, st));
-    float eval_ms = 0.f, count_ms = 0.f;
-    c->base.assign(total, 0);
-    c->last_total = total;
+    Job j;
+    WSE_TRY(job_init(c, j, spaces, n_spaces));
+    if (j.total > out_capacity) return fail(WSE_EINVAL, "out_capacity is smaller than the number of configurations");
+    if (!out && j.total > 0) return fail(WSE_EINVAL, "out is null");
+    if (j.total == 0) return WSE_OK;
+    j.out = out;
+    j.rank_out = rank_out;
     c->last_table_bytes = c->last_launches = c->last_rounds = 0;
-    c->last_E.resize(total);
-    for (int64_t i = 0; i < total; i++) c->last_E[i] = cfgs[i].status == 0 ? cfgs[i].E : 0;
-    if (mode == WSE_BATCHED) {
-        s = run_rounds(c, cfgs, ids, st, &eval_ms, &count_ms);
-        if (s != WSE_OK) return s;
-    } else {
-        std::vector<int64_t> one(1);
-        for (int64_t id : ids) {
-            one[0] = id;
-            s = run_rounds(c, cfgs, one, st, &eval_ms, &count_ms);
-            if (s != WSE_OK) return s;
+    c->events.used = 0;
+    hipEvent_t t0 = c->events.mark(st);
+    wse_status s = job_prepare(c, j, st);
+    if (s != WSE_OK) {
+        j.release();
+        return s;
+    }
+    hipEvent_t t1 = c->events.mark(st);
+    float eval_ms = 0.f, count_ms = 0.f;
+    std::vector<Job*> jobs{&j};
+    std::vector<RoundItem> round;
+    size_t limit = mode == WSE_BATCHED ? SIZE_MAX : 1;
+    while (j.next < j.runnable.size()) {
+        form_round(c, jobs, round, limit);
+        s = run_round(c, round, st, mode == WSE_BATCHED, &eval_ms, &count_ms);
+        if (s != WSE_OK) {
+            j.release();
+            return s;
         }
     }
-    Timer tm2{st, &c->events};
-    tm2.used = tm.used;
-    hipEvent_t t2 = tm2.mark();
-    std::vector<int64_t> first(n_spaces + 1);
-    std::vector<int32_t> cfg_space(total);
-    for (int i = 0; i < n_spaces; i++) {
-        first[i] = sp[i].dev.first;
-        for (int64_t q = 0; q < sp[i].n; q++) cfg_space[sp[i].dev.first + q] = i;
+    hipEvent_t t2 = c->events.mark(st);
+    s = job_finish(c, j, st);
+    hipEvent_t t3 = c->events.mark(st);
+    if (s == WSE_OK) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) s = fail(WSE_EDEVICE, hipGetErrorString(e));
     }
-    first[n_spaces] = total;
-    HIP_TRY(hipMemcpyAsync(c->d_space_first.p, first.data(), first.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(c->d_cfg_space.p, cfg_space.data(), total * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    bool out_dev = is_device_ptr(out);
-    Result* res = out_dev ? (Result*)out : c->d_res.p;
-    HIP_TRY(launch_reduce(c->d_cfgs.p, c->d_ctr.p, total, t, res, st));
-    if (rank_out) {
-        bool rank_dev = is_device_ptr(rank_out);
-        int32_t* rk = rank_dev ? rank_out : c->d_rank.p;
-        HIP_TRY(launch_rank(res, c->d_space_first.p, c->d_cfg_space.p, total, rk, st));
-        if (!rank_dev)
-            HIP_TRY(hipMemcpyAsync(rank_out, rk, total * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    if (s == WSE_OK) {
+        c->timings[0] = elapsed(t0, t1);
+        c->timings[1] = eval_ms;
+        c->timings[2] = count_ms;
+        c->timings[3] = elapsed(t2, t3);
+        c->last_total = j.total;
+        c->last_ctr.resize(j.total);
+        c->last_E.resize(j.total);
+        for (int64_t i = 0; i < j.total; i++) c->last_E[i] = j.cfgs[i].status == 0 ? j.cfgs[i].E : 0;
+        hipError_t e = hipMemcpy(c->last_ctr.data(), j.d_ctr.p, j.total * sizeof(Counters), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) s = fail(WSE_EDEVICE, hipGetErrorString(e));
     }
-    hipEvent_t t3 = tm2.mark();
-    if (!out_dev) HIP_TRY(hipMemcpyAsync(out, res, total * sizeof(Result), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    c->timings[0] = elapsed(t0, t1);
-    c->timings[1] = eval_ms;
-    c->timings[2] = count_ms;
-    c->timings[3] = elapsed(t2, t3);
-    c->timings[4] = eval_ms;
+    j.release();
+    return s;
+}
+
+extern "C" wse_status wse_last_stats(wse_ctx* c, int64_t* stats, int32_t n)
+{
+    if (!c || !stats || n < 0) return fail(WSE_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(c->mu);
+    int64_t evals = 0;
+    for (int64_t i = 0; i < c->last_total; i++)
+        evals += (int64_t)(c->last_ctr[i].lanes_B + c->last_ctr[i].lanes_W + c->last_ctr[i].lanes_L) * c->last_E[i];
+    int64_t v[8] = {evals, c->last_table_bytes, c->last_launches, c->last_rounds, c->last_total, 0, 0, 0};
+    for (int i = 0; i < n && i < 8; i++) stats[i] = v[i];
     return WSE_OK;
 }
 
-static_assert(sizeof(Result) == sizeof(wse_result), "result layout");
+extern "C" wse_status wse_last_evals(wse_ctx* c, int64_t* evals, int64_t n)
+{
+    if (!c || (!evals && n > 0) || n < 0) return fail(WSE_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (n > c->last_total) return fail(WSE_EINVAL, "more entries than configurations");
+    for (int64_t i = 0; i < n; i++)
+        evals[i] = (int64_t)(c->last_ctr[i].lanes_B + c->last_ctr[i].lanes_W + c->last_ctr[i].lanes_L) * c->last_E[i];
+    return WSE_OK;
+}
 
 extern "C" wse_status wse_rhat(wse_ctx* c, const wse_fit* fit, const double* O, double* R, int64_t n,
                                void* stream)
@@ -837,31 +1050,320 @@ extern "C" wse_status wse_rhat(wse_ctx* c, const wse_fit* fit, const double* O, 
     return WSE_OK;
 }
 
-extern "C" wse_status wse_last_stats(wse_ctx* c, int64_t* stats, int32_t n)
+// ---------------------------------------------------------------- tuning
+
+static wse_status check_tuning(const wse_tuning* t)
 {
-    if (!c || !stats || n < 0) return fail(WSE_EINVAL, "null argument");
-    std::lock_guard<std::mutex> lk(c->mu);
-    int64_t evals = 0;
-    if (c->last_total > 0) {
-        std::vector<Counters> k(c->last_total);
-        HIP_TRY(hipMemcpy(k.data(), c->d_ctr.p, c->last_total * sizeof(Counters), hipMemcpyDeviceToHost));
-        for (int64_t i = 0; i < c->last_total; i++)
-            evals += (int64_t)(k[i].lanes_B + k[i].lanes_W + k[i].lanes_L) * c->last_E[i];
-    }
-    int64_t v[8] = {evals, c->last_table_bytes, c->last_launches, c->last_rounds, c->last_total, 0, 0, 0};
-    for (int i = 0; i < n && i < 8; i++) stats[i] = v[i];
+    if (t->lds_slots != 256 && t->lds_slots != 512 && t->lds_slots != 1024)
+        return fail(WSE_EINVAL, "lds_slots must be 256, 512 or 1024");
+    if (t->table_slack_log2 < 1 || t->table_slack_log2 > 3) return fail(WSE_EINVAL, "table_slack_log2 must be 1..3");
+    if (t->item_evals < (1 << 12) || t->item_evals > (1 << 22)) return fail(WSE_EINVAL, "item_evals must be 2^12..2^22");
+    if (t->groups_per_cu < 1 || t->groups_per_cu > 64) return fail(WSE_EINVAL, "groups_per_cu must be 1..64");
     return WSE_OK;
 }
 
-extern "C" wse_status wse_last_evals(wse_ctx* c, int64_t* evals, int64_t n)
+static void get_tuning(const wse_ctx* c, wse_tuning* t)
 {
-    if (!c || (!evals && n > 0) || n < 0) return fail(WSE_EINVAL, "null argument");
+    t->lds_slots = c->lds_slots;
+    t->table_slack_log2 = c->table_slack;
+    t->item_evals = c->target_evals;
+    t->groups_per_cu = c->groups_per_cu;
+    t->pad = 0;
+}
+
+static void put_tuning(wse_ctx* c, const wse_tuning* t)
+{
+    c->lds_slots = t->lds_slots;
+    c->table_slack = t->table_slack_log2;
+    c->target_evals = t->item_evals;
+    c->groups_per_cu = t->groups_per_cu;
+}
+
+extern "C" wse_status wse_get_tuning(wse_ctx* c, wse_tuning* t)
+{
+    if (!c || !t) return fail(WSE_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(c->mu);
-    if (n > c->last_total) return fail(WSE_EINVAL, "more entries than configurations");
-    if (n == 0) return WSE_OK;
-    std::vector<Counters> k(n);
-    HIP_TRY(hipMemcpy(k.data(), c->d_ctr.p, n * sizeof(Counters), hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < n; i++)
-        evals[i] = (int64_t)(k[i].lanes_B + k[i].lanes_W + k[i].lanes_L) * c->last_E[i];
+    get_tuning(c, t);
     return WSE_OK;
 }
+
+extern "C" wse_status wse_set_tuning(wse_ctx* c, const wse_tuning* t)
+{
+    if (!c || !t) return fail(WSE_EINVAL, "null argument");
+    WSE_TRY(check_tuning(t));
+    std::lock_guard<std::mutex> lk(c->mu);
+    put_tuning(c, t);
+    return WSE_OK;
+}
+
+// one batched estimate of a prepared-from-scratch request into device
+// buffers; returns the device time of its evaluation and counting rounds
+static wse_status timed_run(wse_ctx* c, const std::vector<wse_space>& spaces, hipStream_t st, double* ms)
+{
+    Job j;
+    WSE_TRY(job_init(c, j, spaces.data(), (int32_t)spaces.size()));
+    DevBuf<Result> out;
+    HIP_TRY(out.reserve(std::max<int64_t>(j.total, 1)));
+    j.out = (wse_result*)out.p;
+    j.rank_out = nullptr;
+    wse_status s = job_prepare(c, j, st);
+    float ev = 0.f, cn = 0.f;
+    std::vector<Job*> jobs{&j};
+    std::vector<RoundItem> round;
+    auto t0 = std::chrono::steady_clock::now();
+    while (s == WSE_OK && j.next < j.runnable.size()) {
+        form_round(c, jobs, round, SIZE_MAX);
+        s = run_round(c, round, st, true, &ev, &cn);
+    }
+    if (s == WSE_OK) s = job_finish(c, j, st);
+    auto t1 = std::chrono::steady_clock::now();
+    *ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    j.release();
+    out.release();
+    return s;
+}
+
+extern "C" wse_status wse_autotune(wse_ctx* c, const wse_space* spaces, int32_t n_spaces, int32_t sample,
+                                   wse_tuning* chosen)
+{
+    if (!c || !spaces || n_spaces < 1 || sample < 1) return fail(WSE_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_TRY(hipSetDevice(c->device));
+    // a seeded, evenly strided sample of every space
+    std::vector<SpaceHost> sp(n_spaces);
+    int64_t total = 0;
+    {
+        std::lock_guard<std::mutex> rk(c->reg_mu);
+        for (int i = 0; i < n_spaces; i++) {
+            WSE_TRY(build_space(c, &spaces[i], sp[i]));
+            total += sp[i].n;
+        }
+    }
+    std::vector<std::vector<int64_t>> picks(n_spaces);
+    std::vector<wse_space> sub(spaces, spaces + n_spaces);
+    for (int i = 0; i < n_spaces; i++) {
+        int64_t want = std::max<int64_t>(1, (int64_t)sample * sp[i].n / std::max<int64_t>(total, 1));
+        int64_t stride = std::max<int64_t>(1, sp[i].n / want);
+        for (int64_t q = (stride * 7919) % stride; q < sp[i].n && (int64_t)picks[i].size() < want; q += stride)
+            picks[i].push_back(sp[i].expl.empty() ? q : sp[i].expl[q]);
+        sub[i].n_explicit = (int64_t)picks[i].size();
+        sub[i].explicit_idx = picks[i].data();
+    }
+    wse_tuning best;
+    get_tuning(c, &best);
+    double best_ms = 0;
+    WSE_TRY(timed_run(c, sub, c->rs, &best_ms));   // also warms expansions and graphs
+    WSE_TRY(timed_run(c, sub, c->rs, &best_ms));
+    const int lds_c[3] = {256, 512, 1024};
+    const int64_t item_c[3] = {1 << 15, 1 << 17, 1 << 19};
+    const int slack_c[2] = {1, 2};
+    const int groups_c[3] = {8, 16, 32};
+    for (int param = 0; param < 4; param++) {
+        int n_c = param == 2 ? 2 : 3;
+        for (int v = 0; v < n_c; v++) {
+            wse_tuning t = best;
+            if (param == 0) t.lds_slots = lds_c[v];
+            if (param == 1) t.item_evals = item_c[v];
+            if (param == 2) t.table_slack_log2 = slack_c[v];
+            if (param == 3) t.groups_per_cu = groups_c[v];
+            if (memcmp(&t, &best, sizeof(t)) == 0) continue;
+            put_tuning(c, &t);
+            double ms = 0;
+            wse_status s = timed_run(c, sub, c->rs, &ms);
+            if (s == WSE_OK && ms < best_ms) {
+                best = t;
+                best_ms = ms;
+            }
+        }
+        put_tuning(c, &best);
+    }
+    put_tuning(c, &best);
+    if (chosen) *chosen = best;
+    return WSE_OK;
+}
+
+// --------------------------------------------------------------- serving
+
+static void server_loop(wse_server* S)
+{
+    wse_ctx* c = S->ctx;
+    (void)hipSetDevice(c->device);
+    std::unique_lock<std::mutex> lk(S->m);
+    std::vector<RoundItem> round;
+    for (;;) {
+        // admission: FIFO, bounded by the memory budget and the in-flight limit
+        std::vector<std::shared_ptr<Job>> admitted;
+        while (!S->queue.empty() && (int)S->active.size() < S->opts.max_inflight &&
+               S->mem_in_flight + S->queue.front()->mem_bytes <= S->opts.memory_budget_bytes) {
+            std::shared_ptr<Job> j = S->queue.front();
+            S->queue.pop_front();
+            j->t_admit = now_ns();
+            S->mem_in_flight += j->mem_bytes;
+            S->active.push_back(j);
+            admitted.push_back(j);
+        }
+        if (S->active.empty()) {
+            if (S->stopping && S->queue.empty()) break;
+            S->cv.wait(lk);
+            continue;
+        }
+        std::vector<std::shared_ptr<Job>> active = S->active;
+        lk.unlock();
+        std::vector<std::shared_ptr<Job>> finished;
+        {
+            std::lock_guard<std::mutex> dk(c->mu);
+            for (auto& j : admitted) {
+                wse_status s = job_prepare(c, *j, S->stream);
+                if (s != WSE_OK) {
+                    j->status = s;
+                    j->error = g_err;
+                }
+            }
+            std::vector<Job*> runnable;
+            for (auto& j : active)
+                if (j->status == WSE_OK && j->prepared && j->next < j->runnable.size()) runnable.push_back(j.get());
+            if (!runnable.empty()) {
+                form_round(c, runnable, round, SIZE_MAX);
+                float ev = 0.f, cn = 0.f;
+                wse_status s = run_round(c, round, S->stream, true, &ev, &cn);
+                if (s != WSE_OK) {
+                    for (const RoundItem& r : round) {
+                        r.job->status = s;
+                        r.job->error = g_err;
+                    }
+                }
+            }
+            for (auto& j : active) {
+                bool complete = j->status != WSE_OK || (j->prepared && j->next >= j->runnable.size());
+                if (!complete) continue;
+                if (j->status == WSE_OK) {
+                    wse_status s = job_finish(c, *j, S->stream);
+                    if (s != WSE_OK) {
+                        j->status = s;
+                        j->error = g_err;
+                    }
+                }
+                j->release();
+                finished.push_back(j);
+            }
+        }
+        lk.lock();
+        for (auto& j : finished) {
+            j->t_done = now_ns();
+            j->done = true;
+            S->mem_in_flight -= j->mem_bytes;
+            S->active.erase(std::find(S->active.begin(), S->active.end(), j));
+        }
+        if (!finished.empty()) S->cv.notify_all();
+    }
+}
+
+extern "C" wse_status wse_server_start(wse_ctx* c, const wse_server_opts* opts, wse_server** out)
+{
+    if (!c || !out) return fail(WSE_EINVAL, "null argument");
+    *out = nullptr;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->server) return fail(WSE_EBUSY, "the context already has a server");
+    wse_server* S = new (std::nothrow) wse_server();
+    if (!S) return fail(WSE_ENOMEM, "host allocation failed");
+    S->ctx = c;
+    S->opts.memory_budget_bytes = opts && opts->memory_budget_bytes ? opts->memory_budget_bytes : ((size_t)8 << 30);
+    S->opts.max_inflight = opts && opts->max_inflight > 0 ? opts->max_inflight : 64;
+    S->opts.max_queue = opts && opts->max_queue > 0 ? opts->max_queue : 1000000;
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete S;
+        return fail(WSE_EDEVICE, std::string("server stream: ") + hipGetErrorString(e));
+    }
+    S->th = std::thread(server_loop, S);
+    c->server = S;
+    *out = S;
+    return WSE_OK;
+}
+
+extern "C" wse_status wse_submit(wse_server* S, const wse_space* spaces, int32_t n_spaces, wse_result* out,
+                                 int32_t* rank_out, int64_t out_capacity, uint64_t* ticket)
+{
+    if (!S || !ticket || n_spaces < 1 || !spaces) return fail(WSE_EINVAL, "null argument");
+    auto j = std::make_shared<Job>();
+    WSE_TRY(job_init(S->ctx, *j, spaces, n_spaces));   // registry lock only: never waits for a round
+    if (j->total > out_capacity) return fail(WSE_EINVAL, "out_capacity is smaller than the number of configurations");
+    if (!out) return fail(WSE_EINVAL, "out is null");
+    if (j->mem_bytes > S->opts.memory_budget_bytes)
+        return fail(WSE_ENOMEM, "the request alone exceeds the server's memory budget");
+    j->out = out;
+    j->rank_out = rank_out;
+    std::lock_guard<std::mutex> lk(S->m);
+    if (S->stopping) return fail(WSE_EBUSY, "the server is stopping");
+    if ((int64_t)S->queue.size() >= S->opts.max_queue) return fail(WSE_EBUSY, "the request queue is full");
+    j->ticket = S->next_ticket++;
+    j->t_submit = now_ns();
+    S->all[j->ticket] = j;
+    S->queue.push_back(j);
+    *ticket = j->ticket;
+    S->cv.notify_all();
+    return WSE_OK;
+}
+
+extern "C" wse_status wse_poll(wse_server* S, uint64_t ticket, int32_t* done)
+{
+    if (!S || !done) return fail(WSE_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->m);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(WSE_EINVAL, "unknown ticket");
+    *done = it->second->done ? 1 : 0;
+    if (!it->second->done) return WSE_ENOTREADY;
+    if (it->second->status != WSE_OK) return fail(it->second->status, it->second->error);
+    return WSE_OK;
+}
+
+extern "C" wse_status wse_wait(wse_server* S, uint64_t ticket, int64_t timeout_us)
+{
+    if (!S) return fail(WSE_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(S->m);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(WSE_EINVAL, "unknown ticket");
+    std::shared_ptr<Job> j = it->second;
+    if (timeout_us < 0) {
+        S->cv.wait(lk, [&] { return j->done; });
+    } else if (!S->cv.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return j->done; })) {
+        return WSE_ENOTREADY;
+    }
+    if (j->status != WSE_OK) return fail(j->status, j->error);
+    return WSE_OK;
+}
+
+extern "C" wse_status wse_ticket_times(wse_server* S, uint64_t ticket, int64_t* submit_ns, int64_t* admit_ns,
+                                       int64_t* done_ns)
+{
+    if (!S) return fail(WSE_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->m);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(WSE_EINVAL, "unknown ticket");
+    if (submit_ns) *submit_ns = it->second->t_submit;
+    if (admit_ns) *admit_ns = it->second->t_admit;
+    if (done_ns) *done_ns = it->second->t_done;
+    return WSE_OK;
+}
+
+extern "C" wse_status wse_server_stop(wse_server* S)
+{
+    if (!S) return fail(WSE_EINVAL, "null argument");
+    {
+        std::lock_guard<std::mutex> lk(S->m);
+        S->stopping = true;
+        S->cv.notify_all();
+    }
+    if (S->th.joinable()) S->th.join();
+    wse_ctx* c = S->ctx;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        if (c->server == S) c->server = nullptr;
+    }
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    delete S;
+    return WSE_OK;
+}
+
+static_assert(sizeof(Result) == sizeof(wse_result), "result layout");

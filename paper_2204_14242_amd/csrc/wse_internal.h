@@ -109,13 +109,26 @@ struct Counters {
     unsigned long long pad[2];
 };
 
-// a contiguous range of work of one configuration, split into equal items
+// a contiguous range of work of one configuration, split into equal items;
+// the configuration may belong to any request in flight
 struct WorkEntry {
-    int32_t cfg;
+    const Cfg* cfg;
+    Counters* ctr;
+    char* tables;       // the configuration's hash tables in the arena
     int32_t what;       // pass (evaluation) or table (counting)
+    int32_t pad;
     int64_t n_units;    // segments of 64 threads, or table slots
     int64_t per_item;
     int64_t item_start;
+};
+
+// sizes of one arena round, read by the round's kernels from device memory so
+// that one captured graph serves every round
+struct RoundDesc {
+    int64_t fill_bytes;   // arena bytes to clear
+    int64_t items[3];     // work items: evaluation (block+wave), evaluation (layers), counting
+    int32_t first[3];     // first work entry of each launch
+    int32_t n_work[3];    // work entries of each launch
 };
 
 struct Result {  // identical layout to wse_result
@@ -146,14 +159,13 @@ struct ExpandJob {
 };
 
 hipError_t launch_expand(const ExpandJob* jobs_dev, int n_jobs, DevTables t, hipStream_t s);
-hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int64_t lds_slots, hipStream_t s);
+hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2, hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
-hipError_t launch_eval(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr, const WorkEntry* work,
-                       int n_work, int64_t n_items, char* arena, DevTables t, int lds_slots,
-                       int64_t max_groups, hipStream_t s);
-hipError_t launch_count(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr, const WorkEntry* work,
-                        int n_work, int64_t n_items, const char* arena, int64_t max_groups,
-                        hipStream_t s);
+// round launches: sizes come from the device-resident RoundDesc
+hipError_t launch_round_fill(void* arena, const RoundDesc* rd, int64_t max_groups, hipStream_t s);
+hipError_t launch_eval(const WorkEntry* work, const RoundDesc* rd, int which, DevTables t, int lds_slots,
+                       int64_t groups, hipStream_t s);
+hipError_t launch_count(const WorkEntry* work, const RoundDesc* rd, int64_t groups, hipStream_t s);
 hipError_t launch_reduce(const Cfg* cfgs, const Counters* ctr, int64_t n, DevTables t,
                          Result* out, hipStream_t s);
 hipError_t launch_rhat(const double* fit, const double* O, double* R, int64_t n, hipStream_t s);

@@ -308,15 +308,17 @@ __device__ void unit_range(const Cfg& c, const KernelDev& K, const Expansion* X,
     *umax = (int64_t)hi >> log2u;
 }
 
-__device__ int64_t round_cap(int64_t bound, int* log2cap)
+// capacity of a table for at most `bound` keys: the next power of two at or
+// above bound << slack (load factor at most 2^-slack)
+__device__ int64_t round_cap(int64_t bound, int slack, int* log2cap)
 {
-    uint64_t want = (uint64_t)(bound > 32 ? bound : 32) * 2;
+    uint64_t want = (uint64_t)(bound > 32 ? bound : 32) << slack;
     int l = bits_for(want - 1);
     *log2cap = l;
     return (int64_t)1 << l;
 }
 
-__global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t)
+__global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -470,7 +472,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t)
         }
         int64_t bound = (int64_t)keys < ev[q] ? (int64_t)keys : ev[q];
         int l2 = 0;
-        int64_t cap = round_cap(bound, &l2);
+        int64_t cap = round_cap(bound, slack, &l2);
         if (l2 > 32) {
             bad = 2;
             break;
@@ -498,11 +500,11 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t)
     cfgs[i] = c;
 }
 
-hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int64_t, hipStream_t s)
+hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + 127) / 128;
-    hipLaunchKernelGGL(k_decode, dim3((unsigned)blocks), dim3(128), 0, s, cfgs, n, t);
+    hipLaunchKernelGGL(k_decode, dim3((unsigned)blocks), dim3(128), 0, s, cfgs, n, t, table_slack_log2);
     return hipGetLastError();
 }
 
@@ -513,6 +515,20 @@ __global__ void k_fill_zero(uint4* p, int64_t n16)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+__global__ void k_round_fill(uint4* p, const RoundDesc* rd)
+{
+    const int64_t n16 = (rd->fill_bytes + 15) / 16;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+hipError_t launch_round_fill(void* arena, const RoundDesc* rd, int64_t max_groups, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_round_fill, dim3((unsigned)max_groups), dim3(256), 0, s, (uint4*)arena, rd);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s)
@@ -882,13 +898,21 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
     }
 }
 
-__global__ __launch_bounds__(256) void k_eval(const Cfg* __restrict__ cfgs,
-                                              const int64_t* __restrict__ cfg_base,
-                                              Counters* __restrict__ ctr,
-                                              const WorkEntry* __restrict__ work, int n_work,
-                                              int64_t n_items, char* __restrict__ arena, DevTables t,
+__device__ __forceinline__ const void* readfirstlane_ptr(const void* p)
+{
+    uint64_t v = (uint64_t)p;
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (const void*)(((uint64_t)hi << 32) | lo);
+}
+
+__global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work_all,
+                                              const RoundDesc* __restrict__ rd, int which, DevTables t,
                                               int lds_slots)
 {
+    const WorkEntry* work = work_all + rd->first[which];
+    const int n_work = rd->n_work[which];
+    const int64_t n_items = rd->items[which];
     extern __shared__ unsigned long long lds[];
     // the wave index is uniform across the wave; say so, so that everything
     // derived from it (item, configuration) lives in scalar registers
@@ -899,8 +923,9 @@ __global__ __launch_bounds__(256) void k_eval(const Cfg* __restrict__ cfgs,
     unsigned long long* set0 = lds + (size_t)wave * 2 * lds_slots;
     for (int64_t item = (int64_t)blockIdx.x * kWavesPerGroup + wave; item < n_items; item += n_waves) {
         const WorkEntry* W = find_entry(work, n_work, item);
-        const int cfg = __builtin_amdgcn_readfirstlane(W->cfg);
-        const Cfg& c = cfgs[cfg];
+        const Cfg& c = *(const Cfg*)readfirstlane_ptr(W->cfg);
+        Counters* cc = (Counters*)readfirstlane_ptr(W->ctr);
+        char* tables = (char*)readfirstlane_ptr(W->tables);
         const int64_t local = item - W->item_start;
         const int64_t j0 = local * W->per_item;
         const int64_t j1 = j0 + W->per_item < W->n_units ? j0 + W->per_item : W->n_units;
@@ -912,7 +937,7 @@ __global__ __launch_bounds__(256) void k_eval(const Cfg* __restrict__ cfgs,
         P.H = &t.hws[c.hw_id];
         P.exl = c.kind == 0 ? t.expansions[c.expansion_id].ex : nullptr;
         P.exa = c.kind == 1 ? (const ExprA*)P.K->items : nullptr;
-        P.arena = arena + cfg_base[cfg];
+        P.arena = tables;
         P.set0 = set0;
         P.set1 = set0 + lds_slots;
         P.lslots = lds_slots;
@@ -921,7 +946,6 @@ __global__ __launch_bounds__(256) void k_eval(const Cfg* __restrict__ cfgs,
         P.err = 0;
         for (int i = lane; i < 2 * lds_slots; i += kLanes) P.set0[i] = 0;
         wave_fence();
-        Counters* cc = &ctr[cfg];
         if (c.kind == 0) {
             if (pass == PASS_B) run_pass<PASS_B, 0>(P, cc, c.kB, j0, j1);
             else if (pass == PASS_W) run_pass<PASS_W, 0>(P, cc, c.w0, j0, j1);
@@ -934,32 +958,30 @@ __global__ __launch_bounds__(256) void k_eval(const Cfg* __restrict__ cfgs,
     }
 }
 
-hipError_t launch_eval(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr, const WorkEntry* work,
-                       int n_work, int64_t n_items, char* arena, DevTables t, int lds_slots,
-                       int64_t max_groups, hipStream_t s)
+hipError_t launch_eval(const WorkEntry* work, const RoundDesc* rd, int which, DevTables t, int lds_slots,
+                       int64_t groups, hipStream_t s)
 {
-    if (n_items == 0) return hipSuccess;
-    int64_t groups = (n_items + kWavesPerGroup - 1) / kWavesPerGroup;
-    if (groups > max_groups) groups = max_groups;
     size_t shm = (size_t)kWavesPerGroup * 2 * lds_slots * sizeof(unsigned long long);
-    hipLaunchKernelGGL(k_eval, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup), shm, s, cfgs,
-                       cfg_base, ctr, work, n_work, n_items, arena, t, lds_slots);
+    hipLaunchKernelGGL(k_eval, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup), shm, s, work, rd,
+                       which, t, lds_slots);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- counting
 
-__global__ __launch_bounds__(256) void k_count(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr,
-                                               const WorkEntry* work, int n_work, int64_t n_items,
-                                               const char* arena_all)
+__global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ work_all,
+                                               const RoundDesc* __restrict__ rd)
 {
-    const int wave = (int)(threadIdx.x >> 6);
+    const WorkEntry* work = work_all + rd->first[2];
+    const int n_work = rd->n_work[2];
+    const int64_t n_items = rd->items[2];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = lane_id();
     const int64_t n_waves = (int64_t)gridDim.x * kWavesPerGroup;
     for (int64_t item = (int64_t)blockIdx.x * kWavesPerGroup + wave; item < n_items; item += n_waves) {
     const WorkEntry* W = find_entry(work, n_work, item);
-    const Cfg& c = cfgs[W->cfg];
-    const char* arena = arena_all + cfg_base[W->cfg];
+    const Cfg& c = *(const Cfg*)readfirstlane_ptr(W->cfg);
+    const char* arena = (const char*)readfirstlane_ptr(W->tables);
     int q = W->what;
     const TableDesc& T = c.tab[q];
     const unsigned long long* slots = (const unsigned long long*)(arena + T.off);
@@ -1000,7 +1022,7 @@ __global__ __launch_bounds__(256) void k_count(const Cfg* cfgs, const int64_t* c
         ll[d] = wave_sum64(ll[d]);
     }
     if (lane == 0) {
-        Counters* cc = &ctr[W->cfg];
+        Counters* cc = (Counters*)readfirstlane_ptr(W->ctr);
         if (q == T_BSEC) atomicAdd(&cc->comp_ld_B, (unsigned long long)n0);
         else if (q == T_BLINE) atomicAdd(&cc->lines_ld_B, (unsigned long long)n0);
         else if (q == T_WLINE) atomicAdd(&cc->lines_W, (unsigned long long)n0);
@@ -1017,15 +1039,9 @@ __global__ __launch_bounds__(256) void k_count(const Cfg* cfgs, const int64_t* c
     }
 }
 
-hipError_t launch_count(const Cfg* cfgs, const int64_t* cfg_base, Counters* ctr, const WorkEntry* work,
-                        int n_work, int64_t n_items, const char* arena, int64_t max_groups,
-                        hipStream_t s)
+hipError_t launch_count(const WorkEntry* work, const RoundDesc* rd, int64_t groups, hipStream_t s)
 {
-    if (n_items == 0) return hipSuccess;
-    int64_t groups = (n_items + kWavesPerGroup - 1) / kWavesPerGroup;
-    if (groups > max_groups) groups = max_groups;
-    hipLaunchKernelGGL(k_count, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup), 0, s, cfgs,
-                       cfg_base, ctr, work, n_work, n_items, arena);
+    hipLaunchKernelGGL(k_count, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup), 0, s, work, rd);
     return hipGetLastError();
 }
 

@@ -76,6 +76,16 @@ class wse_space(C.Structure):
                 ("n_explicit", C.c_int64), ("explicit_idx", C.POINTER(C.c_int64))]
 
 
+class wse_tuning(C.Structure):
+    _fields_ = [("lds_slots", C.c_int32), ("table_slack_log2", C.c_int32),
+                ("item_evals", C.c_int64), ("groups_per_cu", C.c_int32), ("pad", C.c_int32)]
+
+
+class wse_server_opts(C.Structure):
+    _fields_ = [("memory_budget_bytes", C.c_size_t), ("max_inflight", C.c_int32),
+                ("max_queue", C.c_int32)]
+
+
 _lib = None
 
 
@@ -103,9 +113,23 @@ def lib():
         L.wse_last_evals.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         L.wse_rhat.argtypes = [C.c_void_p, C.POINTER(wse_fit), C.c_void_p, C.c_void_p, C.c_int64,
                                C.c_void_p]
+        L.wse_server_start.argtypes = [C.c_void_p, C.POINTER(wse_server_opts), C.POINTER(C.c_void_p)]
+        L.wse_submit.argtypes = [C.c_void_p, C.POINTER(wse_space), C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_int64, C.POINTER(C.c_uint64)]
+        L.wse_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]
+        L.wse_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int64]
+        L.wse_ticket_times.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.wse_server_stop.argtypes = [C.c_void_p]
+        L.wse_get_tuning.argtypes = [C.c_void_p, C.POINTER(wse_tuning)]
+        L.wse_set_tuning.argtypes = [C.c_void_p, C.POINTER(wse_tuning)]
+        L.wse_autotune.argtypes = [C.c_void_p, C.POINTER(wse_space), C.c_int32, C.c_int32,
+                                   C.POINTER(wse_tuning)]
         for f in ("wse_ctx_create", "wse_kernel_register", "wse_hw_register", "wse_space_size",
                   "wse_estimate", "wse_last_timings", "wse_rhat", "wse_last_stats",
-                  "wse_last_evals"):
+                  "wse_last_evals", "wse_server_start", "wse_submit", "wse_poll", "wse_wait",
+                  "wse_ticket_times", "wse_server_stop", "wse_get_tuning", "wse_set_tuning",
+                  "wse_autotune"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -319,14 +343,93 @@ class Context:
         _check(lib().wse_last_evals(self._ctx, v.ctypes.data, n), self._ctx)
         return v[:n]
 
+    def tuning(self):
+        t = wse_tuning()
+        _check(lib().wse_get_tuning(self._ctx, C.byref(t)), self._ctx)
+        return {"lds_slots": t.lds_slots, "table_slack_log2": t.table_slack_log2,
+                "item_evals": t.item_evals, "groups_per_cu": t.groups_per_cu}
+
+    def set_tuning(self, **kw):
+        cur = self.tuning()
+        cur.update(kw)
+        t = wse_tuning(cur["lds_slots"], cur["table_slack_log2"], cur["item_evals"],
+                       cur["groups_per_cu"], 0)
+        _check(lib().wse_set_tuning(self._ctx, C.byref(t)), self._ctx)
+
+    def autotune(self, specs, sample=32):
+        keep = []
+        arr = self.spaces_array(specs, keep)
+        t = wse_tuning()
+        _check(lib().wse_autotune(self._ctx, arr, len(specs), int(sample), C.byref(t)), self._ctx)
+        return {"lds_slots": t.lds_slots, "table_slack_log2": t.table_slack_log2,
+                "item_evals": t.item_evals, "groups_per_cu": t.groups_per_cu}
+
     def last_timings(self):
         t = (C.c_double * 8)()
         _check(lib().wse_last_timings(self._ctx, t, 8), self._ctx)
         return list(t)
 
 
+class Server:
+    """Continuous-batching server of a context (include/wsest.h, serving)."""
+
+    def __init__(self, ctx, memory_budget_bytes=0, max_inflight=0, max_queue=0):
+        self.ctx = ctx
+        o = wse_server_opts(int(memory_budget_bytes), int(max_inflight), int(max_queue))
+        self._srv = C.c_void_p()
+        _check(lib().wse_server_start(ctx.handle, C.byref(o), C.byref(self._srv)), ctx.handle)
+        self._pending = {}
+
+    def submit(self, specs, want_rank=True):
+        """Queue a request; returns its ticket.  Results land in host arrays
+        retrieved with result(ticket) once it is done."""
+        keep = []
+        arr = self.ctx.spaces_array(specs, keep)
+        n = sum(self.ctx.space_size(k, h, sp) for (k, h, sp) in specs)
+        res = np.zeros(max(n, 1), dtype=RESULT_DTYPE)
+        rk = np.zeros(max(n, 1), dtype=np.int32) if want_rank else None
+        t = C.c_uint64()
+        _check(lib().wse_submit(self._srv, arr, len(specs), res.ctypes.data,
+                                rk.ctypes.data if rk is not None else None, n, C.byref(t)),
+               self.ctx.handle)
+        self._pending[t.value] = (res, rk, n, keep, arr)
+        return t.value
+
+    def poll(self, ticket):
+        d = C.c_int32()
+        st = lib().wse_poll(self._srv, ticket, C.byref(d))
+        if st == WSE_ENOTREADY:
+            return False
+        _check(st, self.ctx.handle)
+        return bool(d.value)
+
+    def wait(self, ticket, timeout_us=-1):
+        st = lib().wse_wait(self._srv, ticket, int(timeout_us))
+        if st == WSE_ENOTREADY:
+            return False
+        _check(st, self.ctx.handle)
+        return True
+
+    def result(self, ticket):
+        res, rk, n, _, _ = self._pending.pop(ticket)
+        return res[:n], (rk[:n] if rk is not None else None)
+
+    def times(self, ticket):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().wse_ticket_times(self._srv, ticket, C.byref(a), C.byref(b), C.byref(c)),
+               self.ctx.handle)
+        return a.value, b.value, c.value
+
+    def stop(self):
+        if self._srv:
+            _check(lib().wse_server_stop(self._srv), self.ctx.handle)
+            self._srv = C.c_void_p()
+
+
 def exported_symbols():
     """Names the public header declares (checked by the CPU test suite)."""
     return ["wse_ctx_create", "wse_ctx_destroy", "wse_status_str", "wse_last_error",
             "wse_kernel_register", "wse_hw_register", "wse_space_size", "wse_estimate",
-            "wse_rhat", "wse_last_timings", "wse_last_stats", "wse_last_evals"]
+            "wse_rhat", "wse_last_timings", "wse_last_stats", "wse_last_evals",
+            "wse_server_start", "wse_submit", "wse_poll", "wse_wait", "wse_ticket_times",
+            "wse_server_stop", "wse_get_tuning", "wse_set_tuning", "wse_autotune"]

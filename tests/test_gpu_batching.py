@@ -1,0 +1,123 @@
+"""Batching: one call over many uneven spaces runs in arena rounds, each a
+replay of the captured round graphs.  Results must not depend on the
+rounds, the graph replays, the tuning or the other spaces in the call."""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2204_14242_amd import workloads as W
+from gpu_common import assert_same, gpu_available, run_oracle
+from helpers import shapes_in
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def small_ctx():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_2204_14242_amd import wsest
+    # a 256 MiB arena forces many rounds
+    c = wsest.Context(0, arena_bytes=256 << 20)
+    yield c
+    c.close()
+
+
+def uneven_specs(ctx):
+    ks, _, sp1 = W.stencil_plain()
+    sp1 = dict(sp1, domains=[(64, 64, 64)], explicit=list(range(0, 230, 3)))
+    sp2 = W.lattice_space([(96, 64, 40)], min_threads=32, max_threads=512, fy=(1, 2), fz=(1, 4),
+                          elems=[4, 8])
+    sp2["explicit"] = sorted(random.Random(5).sample(range(4 * 2 * len(shapes_in(32, 512))), 40))
+    kl = W.lbm_two_phase(8)
+    sp3 = W.lattice_space([(32, 32, 32)], min_threads=64, max_threads=256, elems=[8])
+    stress = W.stress_spaces(seed=5, total=40, max_space=14)
+    specs = [(ks, W.HW1, sp1), (W.star_stencil(2, align=40), W.H2, sp2), (kl, W.H1, sp3)]
+    specs += [(k, hw, sp) for (k, hw, sp) in stress[:3]]
+    reg = []
+    for k, hw, sp in specs:
+        reg.append((ctx.register_kernel(k), ctx.register_hw(hw), sp))
+    return specs, reg
+
+
+def test_many_rounds_graph_equals_eager_and_oracle(small_ctx, orc):
+    from paper_2204_14242_amd import wsest
+    specs, reg = uneven_specs(small_ctx)
+    say("case batching: uneven spaces, small arena, graph rounds")
+    got, grank = small_ctx.estimate(reg, mode=wsest.BATCHED)
+    st = small_ctx.last_stats()
+    assert st["rounds"] > 3, st                  # several graph replays
+    eager, erank = small_ctx.estimate(reg, mode=wsest.PLAIN)
+    assert got.tobytes() == eager.tobytes() and np.array_equal(grank, erank)
+    want, wrank = run_oracle(orc, specs)
+    assert_same(got, want, label="uneven batch")
+    # ranks are per space: compare space by space
+    off = 0
+    for k, hw, sp in specs:
+        n = len(sp["explicit"]) if sp.get("explicit") else orc.space_size(k, sp)
+        _, r = orc.estimate(k, hw, sp)
+        assert np.array_equal(grank[off:off + n], r)
+        off += n
+
+
+def test_each_space_alone_equals_the_mix(small_ctx):
+    from paper_2204_14242_amd import wsest
+    specs, reg = uneven_specs(small_ctx)
+    say("case batching: mix versus spaces alone")
+    mix, mrank = small_ctx.estimate(reg, mode=wsest.BATCHED)
+    off = 0
+    for r in reg:
+        alone, arank = small_ctx.estimate([r], mode=wsest.BATCHED)
+        n = len(alone)
+        assert mix[off:off + n].tobytes() == alone.tobytes()
+        assert np.array_equal(mrank[off:off + n], arank)
+        off += n
+
+
+def test_results_do_not_depend_on_tuning(small_ctx):
+    from paper_2204_14242_amd import wsest
+    specs, reg = uneven_specs(small_ctx)
+    base = small_ctx.tuning()
+    say("case batching: tunings")
+    ref, rrank = small_ctx.estimate(reg, mode=wsest.BATCHED)
+    try:
+        for t in [dict(lds_slots=256, item_evals=1 << 12, groups_per_cu=1),
+                  dict(lds_slots=1024, item_evals=1 << 20, table_slack_log2=3, groups_per_cu=32),
+                  dict(lds_slots=512, item_evals=1 << 15, table_slack_log2=2, groups_per_cu=8)]:
+            small_ctx.set_tuning(**t)
+            got, grank = small_ctx.estimate(reg, mode=wsest.BATCHED)
+            assert got.tobytes() == ref.tobytes(), t
+            assert np.array_equal(grank, rrank), t
+    finally:
+        small_ctx.set_tuning(**base)
+
+
+def test_autotune_keeps_results(small_ctx):
+    from paper_2204_14242_amd import wsest
+    specs, reg = uneven_specs(small_ctx)
+    ref, _ = small_ctx.estimate(reg, mode=wsest.BATCHED)
+    base = small_ctx.tuning()
+    try:
+        say("case batching: autotune")
+        chosen = small_ctx.autotune(reg, sample=24)
+        assert chosen["lds_slots"] in (256, 512, 1024)
+        assert small_ctx.tuning() == chosen
+        got, _ = small_ctx.estimate(reg, mode=wsest.BATCHED)
+        assert got.tobytes() == ref.tobytes()
+    finally:
+        small_ctx.set_tuning(**base)
+
+
+def test_invalid_tuning_is_rejected(small_ctx):
+    from paper_2204_14242_amd import wsest
+    with pytest.raises(wsest.WseError):
+        small_ctx.set_tuning(lds_slots=300)
+    with pytest.raises(wsest.WseError):
+        small_ctx.set_tuning(groups_per_cu=0)
