@@ -197,6 +197,7 @@ struct wse_ctx {
     char* arena = nullptr;
     size_t arena_bytes = 0;
     int n_cu = 256;
+    size_t max_lds = 64 * 1024;  // LDS bytes one workgroup may allocate
     std::mutex mu;      // execution resources: arena, expansions, graphs, round buffers
     std::mutex reg_mu;  // the registries below; taken after mu, never before it
     std::vector<KernelHost> kernels;
@@ -217,10 +218,10 @@ struct wse_ctx {
     int64_t graph_groups = 0;
     int graph_lds = 0;
     // tuning
-    int lds_slots = 512;
+    int lds_slots = 2048;
     int table_slack = 1;
     int groups_per_cu = 16;
-    int64_t target_evals = 1 << 17;
+    int64_t target_evals = 1 << 19;
     bool dirty_kernels = false, dirty_hws = false;
     bool progress = false;  // WSE_PROGRESS=1: one stderr line per arena round
     EventPool events, round_events;
@@ -286,7 +287,10 @@ wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out)
         return fail(WSE_ENOMEM, std::string("arena allocation failed: ") + hipGetErrorString(e));
     }
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->n_cu = prop.multiProcessorCount;
+        c->max_lds = prop.sharedMemPerBlock;
+    }
     const char* pg = std::getenv("WSE_PROGRESS");
     c->progress = pg && pg[0] == '1';
     e = hipStreamCreateWithFlags(&c->rs, hipStreamNonBlocking);
@@ -853,7 +857,10 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
         int64_t base = used;
         used += g.table_bytes;
         int64_t spb = g.segs_per_block;
+        // segments per work item: a multiple of the workgroup's waves, which
+        // walk an item's segments in lockstep
         int64_t per = std::max<int64_t>(1, c->target_evals / ((int64_t)kLanes * std::max(1, g.E)));
+        per = (per + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
         auto add = [&](int which, int what, int64_t units, int64_t per_item) {
             if (units <= 0) return;
             WorkEntry e;
@@ -1052,10 +1059,12 @@ extern "C" wse_status wse_rhat(wse_ctx* c, const wse_fit* fit, const double* O, 
 
 // ---------------------------------------------------------------- tuning
 
-static wse_status check_tuning(const wse_tuning* t)
+static wse_status check_tuning(const wse_ctx* c, const wse_tuning* t)
 {
-    if (t->lds_slots != 256 && t->lds_slots != 512 && t->lds_slots != 1024)
-        return fail(WSE_EINVAL, "lds_slots must be 256, 512 or 1024");
+    if (t->lds_slots != 1024 && t->lds_slots != 2048 && t->lds_slots != 4096)
+        return fail(WSE_EINVAL, "lds_slots must be 1024, 2048 or 4096");
+    if (eval_lds_bytes(t->lds_slots) > c->max_lds)
+        return fail(WSE_EINVAL, "lds_slots needs more LDS than a workgroup may allocate on this device");
     if (t->table_slack_log2 < 1 || t->table_slack_log2 > 3) return fail(WSE_EINVAL, "table_slack_log2 must be 1..3");
     if (t->item_evals < (1 << 12) || t->item_evals > (1 << 22)) return fail(WSE_EINVAL, "item_evals must be 2^12..2^22");
     if (t->groups_per_cu < 1 || t->groups_per_cu > 64) return fail(WSE_EINVAL, "groups_per_cu must be 1..64");
@@ -1090,7 +1099,7 @@ extern "C" wse_status wse_get_tuning(wse_ctx* c, wse_tuning* t)
 extern "C" wse_status wse_set_tuning(wse_ctx* c, const wse_tuning* t)
 {
     if (!c || !t) return fail(WSE_EINVAL, "null argument");
-    WSE_TRY(check_tuning(t));
+    WSE_TRY(check_tuning(c, t));
     std::lock_guard<std::mutex> lk(c->mu);
     put_tuning(c, t);
     return WSE_OK;
@@ -1154,8 +1163,8 @@ extern "C" wse_status wse_autotune(wse_ctx* c, const wse_space* spaces, int32_t 
     double best_ms = 0;
     WSE_TRY(timed_run(c, sub, c->rs, &best_ms));   // also warms expansions and graphs
     WSE_TRY(timed_run(c, sub, c->rs, &best_ms));
-    const int lds_c[3] = {256, 512, 1024};
-    const int64_t item_c[3] = {1 << 15, 1 << 17, 1 << 19};
+    const int lds_c[3] = {1024, 2048, 4096};
+    const int64_t item_c[3] = {1 << 17, 1 << 19, 1 << 21};
     const int slack_c[2] = {1, 2};
     const int groups_c[3] = {8, 16, 32};
     for (int param = 0; param < 4; param++) {
@@ -1166,7 +1175,7 @@ extern "C" wse_status wse_autotune(wse_ctx* c, const wse_space* spaces, int32_t 
             if (param == 1) t.item_evals = item_c[v];
             if (param == 2) t.table_slack_log2 = slack_c[v];
             if (param == 3) t.groups_per_cu = groups_c[v];
-            if (memcmp(&t, &best, sizeof(t)) == 0) continue;
+            if (memcmp(&t, &best, sizeof(t)) == 0 || eval_lds_bytes(t.lds_slots) > c->max_lds) continue;
             put_tuning(c, &t);
             double ms = 0;
             wse_status s = timed_run(c, sub, c->rs, &ms);

@@ -163,6 +163,8 @@ hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 // round launches: sizes come from the device-resident RoundDesc
 hipError_t launch_round_fill(void* arena, const RoundDesc* rd, int64_t max_groups, hipStream_t s);
+// dynamic LDS bytes of one evaluation workgroup
+size_t eval_lds_bytes(int lds_slots);
 hipError_t launch_eval(const WorkEntry* work, const RoundDesc* rd, int which, DevTables t, int lds_slots,
                        int64_t groups, hipStream_t s);
 hipError_t launch_count(const WorkEntry* work, const RoundDesc* rd, int64_t groups, hipStream_t s);

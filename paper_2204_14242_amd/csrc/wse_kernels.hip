@@ -624,21 +624,25 @@ struct PassCtx {
     const ExprL* exl;
     const ExprA* exa;
     char* arena;
-    unsigned long long* set0;
+    unsigned long long* set0;  // LDS hash sets shared by the workgroup's waves
     unsigned long long* set1;
+    uint32_t* cnt;             // [2][waves] new-key counts of one step, by step parity
     int lslots, llog;
-    int fill0, fill1;
+    int wave;
+    int fill0, fill1;          // running fills of the sets, the same in every wave
+    int step;
     uint64_t err;
 };
 
-// move every entry of a per-wave LDS set into the configuration's HBM table
+// Move every entry of a shared LDS set into the configuration's HBM table;
+// all threads of the workgroup take part.  The caller synchronises before
+// further inserts.
 __device__ void flush_set(PassCtx& P, unsigned long long* set, int q, int mode, bool probe_wsec)
 {
     const TableDesc& T = P.c->tab[q];
     unsigned long long* slots = (unsigned long long*)(P.arena + T.off);
-    int lane = lane_id();
     bool overflow = false;
-    for (int i = lane; i < P.lslots; i += kLanes) {
+    for (int i = (int)threadIdx.x; i < P.lslots; i += (int)blockDim.x) {
         unsigned long long e = set[i];
         if (e == 0) continue;
         set[i] = 0;
@@ -659,12 +663,50 @@ __device__ void flush_set(PassCtx& P, unsigned long long* set, int q, int mode, 
         }
     }
     if (__ballot(overflow)) P.err |= 2;
-    wave_fence();
 }
 
-// Insert one entry per lane (0 = nothing) into a per-wave LDS set.  A lane
+template <int PASS>
+__device__ void flush_both(PassCtx& P, bool do_sec)
+{
+    if (PASS == PASS_B) {
+        flush_set(P, P.set0, T_BSEC, MODE_SET, false);
+        flush_set(P, P.set1, T_BLINE, MODE_SET, false);
+    } else if (PASS == PASS_W) {
+        flush_set(P, P.set0, T_WSEC, MODE_OR, false);
+        flush_set(P, P.set1, T_WLINE, MODE_SET, false);
+    } else {
+        if (do_sec) flush_set(P, P.set0, T_WSEC, MODE_MAX, true);
+        flush_set(P, P.set1, T_LLINE, MODE_MAX, false);
+    }
+}
+
+// End of one instruction step of the workgroup: share the waves' new-key
+// counts through LDS (double-buffered by step parity, so no wave overwrites
+// counts another still reads) and flush both sets together when the next
+// step could fill either beyond half.  Every wave calls this equally often.
+template <int PASS>
+__device__ __forceinline__ void step_sync(PassCtx& P, int new0, int new1, bool do_sec)
+{
+    const int par = P.step & 1;
+    if (lane_id() == 0) P.cnt[par * kWavesPerGroup + P.wave] = (uint32_t)new0 | ((uint32_t)new1 << 16);
+    __syncthreads();
+    for (int w = 0; w < kWavesPerGroup; w++) {
+        uint32_t v = P.cnt[par * kWavesPerGroup + w];
+        P.fill0 += (int)(v & 0xffffu);
+        P.fill1 += (int)(v >> 16);
+    }
+    P.step++;
+    const int thr = P.lslots / 2 - kLanes * kWavesPerGroup;
+    if (P.fill0 > thr || P.fill1 > thr) {
+        flush_both<PASS>(P, do_sec);
+        __syncthreads();
+        P.fill0 = P.fill1 = 0;
+    }
+}
+
+// Insert one entry per lane (0 = nothing) into a shared LDS set.  A lane
 // whose left neighbour in its 16-lane row holds the same entry skips it; the
-// set merges the rest.  Returns the number of keys new to the set.
+// set merges the rest.  Returns the number of keys this wave made new.
 __device__ __forceinline__ int lds_add(PassCtx& P, unsigned long long* set, uint64_t entry, int pb,
                                        int mode)
 {
@@ -680,7 +722,7 @@ __device__ __forceinline__ int lds_add(PassCtx& P, unsigned long long* set, uint
 
 // constants of one instruction, one instruction per lane for a chunk of 64
 struct IConst {
-    int64_t S;       // lattice: align + elem * c0; affine: align + elem * c0
+    int64_t S;       // align + elem * c0
     int64_t fs, fl;  // field * span + 1 of the pass's sector and line tables
     int32_t st, elem;
     int64_t kt[3], kb[3];  // affine: index coefficients of tid and bid
@@ -722,6 +764,10 @@ __device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, const Tab
 
 __device__ __forceinline__ int32_t readlane32(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// One pass (representative block, wave or layer interval) over the segments
+// [j0, j1) of 64 consecutive threads.  The workgroup's waves take
+// consecutive segments in lockstep, one instruction per step, so that the
+// keys they share meet in the shared LDS sets.
 template <int PASS, int KIND>
 __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, int64_t j1)
 {
@@ -742,7 +788,6 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
     const int64_t f1 = c.fold[1], f2 = c.fold[2];
     const int64_t smin = c.smin;
     const int tag_bits = c.tag_bits;
-    const int thr = P.lslots / 2 - kLanes;
     int64_t acc_up_ld = 0, acc_up_st = 0, acc_cyc = 0, acc_lanes = 0, acc_warps = 0;
     const TableDesc& TS = c.tab[PASS == PASS_B ? T_BSEC : T_WSEC];
     const TableDesc& TL = c.tab[PASS == PASS_W ? T_WLINE : (PASS == PASS_B ? T_BLINE : T_LLINE)];
@@ -762,33 +807,37 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
         else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}};
         const int32_t meta = ic.st | (ic.elem << 1);
 
-        // first segment of the item: block k, segment sgi, block coordinates
-        int64_t k = k_lo + j0 / spb;
-        int sgi = (int)(j0 % spb);
+        // this wave's first segment: block k, segment sgi, block coordinates
+        int64_t jw = j0 + P.wave;
+        int64_t k = k_lo + jw / spb;
+        int sgi = (int)(jw % spb);
         int64_t bx = k % nb0, by = (k / nb0) % nb1, bz = k / (nb0 * nb1);
-        for (int64_t j = j0; j < j1; j++) {
+        for (int64_t jg = j0; jg < j1; jg += kWavesPerGroup) {
+            const bool seg_ok = jg + P.wave < j1;
             const int64_t t = (int64_t)sgi * kLanes + lane;
             const bool inb = t < Pthr;
             const int64_t tx = t & (b0 - 1), ty = (t >> lb0) & (b1 - 1), tz = t >> (lb0 + lb1);
             const int64_t gx = bx * b0 + tx, gy = by * b1 + ty, gz = bz * b2 + tz;
-            const bool valid = inb && gx < T0 && gy < T1 && gz < T2;
+            const bool valid = seg_ok && inb && gx < T0 && gy < T1 && gz < T2;
             const uint64_t vmask = __ballot(valid);
             const int64_t kcur = k;
             const int64_t bcur[3] = {bx, by, bz};
             const int64_t tcur[3] = {tx, ty, tz};
-            // advance to the next segment
-            if (++sgi == spb) {
-                sgi = 0;
-                k++;
-                if (++bx == nb0) {
-                    bx = 0;
-                    if (++by == nb1) {
-                        by = 0;
-                        bz++;
+            // advance by one segment per wave of the workgroup
+            for (int step = 0; step < kWavesPerGroup; step++) {
+                if (++sgi == spb) {
+                    sgi = 0;
+                    k++;
+                    if (++bx == nb0) {
+                        bx = 0;
+                        if (++by == nb1) {
+                            by = 0;
+                            bz++;
+                        }
                     }
                 }
             }
-            if (e0 == 0) {
+            if (e0 == 0 && seg_ok) {
                 acc_lanes += __popcll(vmask);
                 if (PASS == PASS_B) {
                     const int ws = 1 << log2_warp;
@@ -798,89 +847,77 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
                     }
                 }
             }
-            if (vmask == 0) continue;
             const uint64_t tag = PASS == PASS_L ? (uint64_t)(kcur - smin + 1) : 0;
             int64_t base = 0;
             if (KIND == 0) base = (gx + g) + sy * (f1 * gy + g) + sz * (f2 * gz + g);
             const int64_t ubase = uelem ? base * uelem : 0;
 
             for (int q = 0; q < n_in; q++) {
-                if (P.fill0 > thr || P.fill1 > thr) {
-                    if (PASS == PASS_B) {
-                        flush_set(P, P.set0, T_BSEC, MODE_SET, false);
-                        flush_set(P, P.set1, T_BLINE, MODE_SET, false);
-                    } else if (PASS == PASS_W) {
-                        flush_set(P, P.set0, T_WSEC, MODE_OR, false);
-                        flush_set(P, P.set1, T_WLINE, MODE_SET, false);
+                int new0 = 0, new1 = 0;
+                if (vmask) {
+                    const int64_t S = readlane64(ic.S, q);
+                    const int32_t m = readlane32(meta, q);
+                    const int st = m & 1;
+                    int64_t addr;
+                    if (KIND == 0) {
+                        addr = uelem ? ubase + S : base * (int64_t)(m >> 1) + S;
                     } else {
-                        flush_set(P, P.set0, T_WSEC, MODE_MAX, true);
-                        flush_set(P, P.set1, T_LLINE, MODE_MAX, false);
+                        int64_t idx = 0;
+                        for (int d = 0; d < 3; d++)
+                            idx += readlane64(ic.kt[d], q) * tcur[d] + readlane64(ic.kb[d], q) * bcur[d];
+                        addr = S + (int64_t)(m >> 1) * idx;
                     }
-                    P.fill0 = P.fill1 = 0;
-                }
-                const int64_t S = readlane64(ic.S, q);
-                const int32_t m = readlane32(meta, q);
-                const int st = m & 1;
-                int64_t addr;
-                if (KIND == 0) {
-                    addr = uelem ? ubase + S : base * (int64_t)(m >> 1) + S;
-                } else {
-                    int64_t idx = 0;
-                    for (int d = 0; d < 3; d++)
-                        idx += readlane64(ic.kt[d], q) * tcur[d] + readlane64(ic.kb[d], q) * bcur[d];
-                    addr = S + (int64_t)(m >> 1) * idx;
-                }
-                const int64_t sec = addr >> ls;
-                const int64_t line = addr >> ll;
-                const int64_t us = sec - umin_s, ul = line - umin_l;
-                if (PASS == PASS_B) {
-                    int64_t dcount = warp_distinct(valid, sec, log2_warp);
-                    if (st) acc_up_st += dcount;
-                    else acc_up_ld += dcount;
-                    acc_cyc += group_cycles(valid, addr >> log2_bank, log2_group, n_banks, pair_words);
-                    if (!st) {
+                    const int64_t sec = addr >> ls;
+                    const int64_t line = addr >> ll;
+                    const int64_t us = sec - umin_s, ul = line - umin_l;
+                    if (PASS == PASS_B) {
+                        int64_t dcount = warp_distinct(valid, sec, log2_warp);
+                        if (st) acc_up_st += dcount;
+                        else acc_up_ld += dcount;
+                        acc_cyc += group_cycles(valid, addr >> log2_bank, log2_group, n_banks, pair_words);
+                        if (!st) {
+                            bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
+                            if (__ballot(valid && !ok)) P.err |= 1;
+                            bool act = valid && ok;
+                            uint64_t ks = act ? (uint64_t)(us + readlane64(ic.fs, q)) : 0;
+                            uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
+                            new0 = lds_add(P, P.set0, ks, 0, MODE_SET);
+                            new1 = lds_add(P, P.set1, kl, 0, MODE_SET);
+                        }
+                    } else if (PASS == PASS_W) {
+                        if (st) acc_up_st += warp_distinct(valid, sec, log2_warp);
                         bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
                         if (__ballot(valid && !ok)) P.err |= 1;
                         bool act = valid && ok;
-                        uint64_t ks = act ? (uint64_t)(us + readlane64(ic.fs, q)) : 0;
+                        uint64_t ks =
+                            act ? (((uint64_t)(us + readlane64(ic.fs, q)) << 2) | (st ? 2u : 1u)) : 0;
                         uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
-                        P.fill0 += lds_add(P, P.set0, ks, 0, MODE_SET);
-                        P.fill1 += lds_add(P, P.set1, kl, 0, MODE_SET);
-                    }
-                } else if (PASS == PASS_W) {
-                    if (st) acc_up_st += warp_distinct(valid, sec, log2_warp);
-                    bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
-                    if (__ballot(valid && !ok)) P.err |= 1;
-                    bool act = valid && ok;
-                    uint64_t ks = act ? (((uint64_t)(us + readlane64(ic.fs, q)) << 2) | (st ? 2u : 1u)) : 0;
-                    uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
-                    P.fill0 += lds_add(P, P.set0, ks, sec_pb, sec_mode);
-                    P.fill1 += lds_add(P, P.set1, kl, line_pb, line_mode);
-                } else {
-                    bool ok = (uint64_t)ul < (uint64_t)span_l;
-                    if (__ballot(valid && !ok)) P.err |= 1;
-                    uint64_t kl = (valid && ok) ? ((((uint64_t)(ul + readlane64(ic.fl, q))) << line_pb) | tag) : 0;
-                    P.fill1 += lds_add(P, P.set1, kl, line_pb, line_mode);
-                    if (do_sec) {
-                        bool in = valid && (uint64_t)us < (uint64_t)span_s;
-                        uint64_t ks = in ? ((((uint64_t)(us + readlane64(ic.fs, q))) << sec_pb) | tag) : 0;
-                        P.fill0 += lds_add(P, P.set0, ks, sec_pb, sec_mode);
+                        new0 = lds_add(P, P.set0, ks, sec_pb, sec_mode);
+                        new1 = lds_add(P, P.set1, kl, line_pb, line_mode);
+                    } else {
+                        bool ok = (uint64_t)ul < (uint64_t)span_l;
+                        if (__ballot(valid && !ok)) P.err |= 1;
+                        uint64_t kl = (valid && ok)
+                                          ? ((((uint64_t)(ul + readlane64(ic.fl, q))) << line_pb) | tag)
+                                          : 0;
+                        new1 = lds_add(P, P.set1, kl, line_pb, line_mode);
+                        if (do_sec) {
+                            bool in = valid && (uint64_t)us < (uint64_t)span_s;
+                            uint64_t ks =
+                                in ? ((((uint64_t)(us + readlane64(ic.fs, q))) << sec_pb) | tag) : 0;
+                            new0 = lds_add(P, P.set0, ks, sec_pb, sec_mode);
+                        }
                     }
                 }
+                step_sync<PASS>(P, new0, new1, do_sec);
             }
         }
     }
-    // final flush and accumulators
-    if (PASS == PASS_B) {
-        flush_set(P, P.set0, T_BSEC, MODE_SET, false);
-        flush_set(P, P.set1, T_BLINE, MODE_SET, false);
-    } else if (PASS == PASS_W) {
-        flush_set(P, P.set0, T_WSEC, MODE_OR, false);
-        flush_set(P, P.set1, T_WLINE, MODE_SET, false);
-    } else {
-        if (do_sec) flush_set(P, P.set0, T_WSEC, MODE_MAX, true);
-        flush_set(P, P.set1, T_LLINE, MODE_MAX, false);
-    }
+    // final flush of the item and accumulators
+    __syncthreads();
+    flush_both<PASS>(P, do_sec);
+    __syncthreads();
+    P.fill0 = P.fill1 = 0;
     if (lane == 0) {
         if (PASS == PASS_B) {
             atomicAdd(&ctr->lanes_B, (unsigned long long)acc_lanes);
@@ -906,22 +943,25 @@ __device__ __forceinline__ const void* readfirstlane_ptr(const void* p)
     return (const void*)(((uint64_t)hi << 32) | lo);
 }
 
+// Evaluation kernel: resident workgroups loop over the round's work items;
+// the four waves of a workgroup share two LDS hash sets of lds_slots
+// entries and cooperate on one item at a time.
 __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work_all,
                                               const RoundDesc* __restrict__ rd, int which, DevTables t,
                                               int lds_slots)
 {
+    extern __shared__ unsigned long long lds[];
     const WorkEntry* work = work_all + rd->first[which];
     const int n_work = rd->n_work[which];
     const int64_t n_items = rd->items[which];
-    extern __shared__ unsigned long long lds[];
-    // the wave index is uniform across the wave; say so, so that everything
-    // derived from it (item, configuration) lives in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = lane_id();
-    const int64_t n_waves = (int64_t)gridDim.x * kWavesPerGroup;
     const int llog = 31 - __clz(lds_slots);
-    unsigned long long* set0 = lds + (size_t)wave * 2 * lds_slots;
-    for (int64_t item = (int64_t)blockIdx.x * kWavesPerGroup + wave; item < n_items; item += n_waves) {
+    unsigned long long* set0 = lds;
+    unsigned long long* set1 = lds + lds_slots;
+    uint32_t* cnt = (uint32_t*)(lds + 2 * (size_t)lds_slots);
+    for (int i = (int)threadIdx.x; i < 2 * lds_slots; i += (int)blockDim.x) lds[i] = 0;
+    __syncthreads();
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const WorkEntry* W = find_entry(work, n_work, item);
         const Cfg& c = *(const Cfg*)readfirstlane_ptr(W->cfg);
         Counters* cc = (Counters*)readfirstlane_ptr(W->ctr);
@@ -939,13 +979,14 @@ __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work
         P.exa = c.kind == 1 ? (const ExprA*)P.K->items : nullptr;
         P.arena = tables;
         P.set0 = set0;
-        P.set1 = set0 + lds_slots;
+        P.set1 = set1;
+        P.cnt = cnt;
         P.lslots = lds_slots;
         P.llog = llog;
+        P.wave = wave;
         P.fill0 = P.fill1 = 0;
+        P.step = 0;
         P.err = 0;
-        for (int i = lane; i < 2 * lds_slots; i += kLanes) P.set0[i] = 0;
-        wave_fence();
         if (c.kind == 0) {
             if (pass == PASS_B) run_pass<PASS_B, 0>(P, cc, c.kB, j0, j1);
             else if (pass == PASS_W) run_pass<PASS_W, 0>(P, cc, c.w0, j0, j1);
@@ -958,12 +999,16 @@ __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work
     }
 }
 
+size_t eval_lds_bytes(int lds_slots)
+{
+    return 2 * (size_t)lds_slots * sizeof(unsigned long long) + 2 * kWavesPerGroup * sizeof(uint32_t);
+}
+
 hipError_t launch_eval(const WorkEntry* work, const RoundDesc* rd, int which, DevTables t, int lds_slots,
                        int64_t groups, hipStream_t s)
 {
-    size_t shm = (size_t)kWavesPerGroup * 2 * lds_slots * sizeof(unsigned long long);
-    hipLaunchKernelGGL(k_eval, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup), shm, s, work, rd,
-                       which, t, lds_slots);
+    hipLaunchKernelGGL(k_eval, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup), eval_lds_bytes(lds_slots), s,
+                       work, rd, which, t, lds_slots);
     return hipGetLastError();
 }
 

@@ -88,9 +88,9 @@ def test_results_do_not_depend_on_tuning(small_ctx):
     say("case batching: tunings")
     ref, rrank = small_ctx.estimate(reg, mode=wsest.BATCHED)
     try:
-        for t in [dict(lds_slots=256, item_evals=1 << 12, groups_per_cu=1),
-                  dict(lds_slots=1024, item_evals=1 << 20, table_slack_log2=3, groups_per_cu=32),
-                  dict(lds_slots=512, item_evals=1 << 15, table_slack_log2=2, groups_per_cu=8)]:
+        for t in [dict(lds_slots=1024, item_evals=1 << 12, groups_per_cu=1),
+                  dict(lds_slots=4096, item_evals=1 << 22, table_slack_log2=3, groups_per_cu=32),
+                  dict(lds_slots=2048, item_evals=1 << 15, table_slack_log2=2, groups_per_cu=8)]:
             small_ctx.set_tuning(**t)
             got, grank = small_ctx.estimate(reg, mode=wsest.BATCHED)
             assert got.tobytes() == ref.tobytes(), t
@@ -107,7 +107,7 @@ def test_autotune_keeps_results(small_ctx):
     try:
         say("case batching: autotune")
         chosen = small_ctx.autotune(reg, sample=24)
-        assert chosen["lds_slots"] in (256, 512, 1024)
+        assert chosen["lds_slots"] in (1024, 2048, 4096)
         assert small_ctx.tuning() == chosen
         got, _ = small_ctx.estimate(reg, mode=wsest.BATCHED)
         assert got.tobytes() == ref.tobytes()
@@ -118,6 +118,6 @@ def test_autotune_keeps_results(small_ctx):
 def test_invalid_tuning_is_rejected(small_ctx):
     from paper_2204_14242_amd import wsest
     with pytest.raises(wsest.WseError):
-        small_ctx.set_tuning(lds_slots=300)
+        small_ctx.set_tuning(lds_slots=512)
     with pytest.raises(wsest.WseError):
         small_ctx.set_tuning(groups_per_cu=0)
