@@ -38,7 +38,76 @@ def parse():
     p.add_argument("--arena-gib", type=float, default=96.0)
     p.add_argument("--cpu-budget-s", type=float, default=20.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--plain-sample", type=int, default=192,
+                   help="configurations of the workload estimated in plain and batched form side by side")
+    p.add_argument("--serve-requests", type=int, default=24,
+                   help="requests of the seeded Poisson trace replayed through the server (0 = skip)")
     return p.parse_args()
+
+
+def plain_vs_batched(ctx, kid, hid, space, n, sample):
+    """The same seeded sample of the workload estimated one configuration per
+    launch sequence (plain) and batched; both must agree byte for byte."""
+    import numpy as np
+    from paper_2204_14242_amd import wsest
+    rng = np.random.default_rng(11)
+    idx = sorted(int(v) for v in rng.choice(n, size=min(sample, n), replace=False))
+    spec = [(kid, hid, dict(space, explicit=idx))]
+    rates, res = {}, {}
+    for name, mode in (("plain", wsest.PLAIN), ("batched", wsest.BATCHED)):
+        ctx.estimate(spec, mode=mode)
+        t0 = time.perf_counter()
+        res[name], _ = ctx.estimate(spec, mode=mode)
+        rates[name] = len(idx) / (time.perf_counter() - t0)
+        print(f"{name} sample of {len(idx)} done", file=sys.stderr, flush=True)
+    if res["plain"].tobytes() != res["batched"].tobytes():
+        raise SystemExit("plain and batched results differ")
+    return {"sample": f"{len(idx)} seeded configurations of the workload",
+            "plain_configs_per_s": rates["plain"], "batched_configs_per_s": rates["batched"],
+            "batched_over_plain": rates["batched"] / rates["plain"], "identical": True}
+
+
+def served(ctx, n_requests):
+    """Replay the first requests of the seeded Poisson trace (200 requests/s,
+    sizes log-uniform 10..50,000, three kernel families, three HW sets)
+    through the continuous-batching server, open loop."""
+    import numpy as np
+    from paper_2204_14242_amd import workloads as W
+    from paper_2204_14242_amd import wsest
+    fams = [W.stencil_plain(), W.stencil_batched(), W.lbm_batched()]
+    kids, spaces = [], []
+    hids = {name: ctx.register_hw(hw) for name, hw in W.HW_SETS.items()}
+    for k, _, sp in fams:
+        kids.append(ctx.register_kernel(k))
+        spaces.append(sp)
+    sizes = [ctx.space_size(kids[i], hids["H3"], spaces[i]) for i in range(3)]
+    reqs = W.serving_requests(sizes, seed=4, n_requests=n_requests, rate=200.0)
+    srv = wsest.Server(ctx, memory_budget_bytes=8 << 30, max_inflight=8)
+    tickets = []
+    try:
+        t0 = time.perf_counter()
+        for r in reqs:
+            delay = t0 + r["t_arrival"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            f = r["family"]
+            tickets.append(srv.submit([(kids[f], hids[r["hw"]], dict(spaces[f], explicit=r["explicit"]))],
+                                      want_rank=True))
+        for i, t in enumerate(tickets):
+            if not srv.wait(t, timeout_us=600_000_000):
+                raise SystemExit(f"served request {i} did not finish")
+            print(f"served request {i} done ({len(reqs[i]['explicit'])} configurations)",
+                  file=sys.stderr, flush=True)
+        times = [srv.times(t) for t in tickets]
+    finally:
+        srv.stop()
+    lat_ms = np.array([(d - s) / 1e6 for s, _, d in times])
+    total = sum(len(r["explicit"]) for r in reqs)
+    span_s = (max(d for _, _, d in times) - min(s for s, _, _ in times)) / 1e9
+    return {"requests": len(reqs), "configs": total, "configs_per_s": total / span_s,
+            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+            "trace": "first requests of the seed-4 Poisson trace at 200 requests/s, replayed open loop; "
+                     "offered load exceeds capacity, so latencies include queueing"}
 
 
 def cpu_baseline(kernel, hw, space, per_config_evals, budget_s):
@@ -144,6 +213,10 @@ def main():
                      "kernel": "k_eval", "avg_launch_ms": eval_ms / max(launches, 1),
                      "ops_per_eval": OPS_PER_EVAL},
     }
+    if a.plain_sample > 0:
+        line["plain_vs_batched"] = plain_vs_batched(ctx, kid, hid, space, n, a.plain_sample)
+    if a.serve_requests > 0:
+        line["served"] = served(ctx, a.serve_requests)
     if not a.no_cpu_baseline:
         # per-configuration evaluation counts of the workload, from the last GPU step
         per = ctx.last_evals(n).astype(np.float64)

@@ -205,14 +205,17 @@ typedef struct {
     int32_t table_slack_log2;   /* HBM hash tables hold at least 2^slack slots per key bound (1..3) */
     int64_t item_evals;         /* address evaluations per work item of a workgroup (2^12 .. 2^22) */
     int32_t groups_per_cu;      /* resident-loop workgroups per compute unit (1 .. 64) */
-    int32_t pad;
+    int32_t bitmap_log2;        /* a configuration keeps its sets as bitmaps instead of hash tables
+                                   when every set's key range is at most 2^bitmap_log2 times the
+                                   evaluations that reach it (and below 2^32 keys); 0 = always
+                                   hash tables (0 .. 8) */
 } wse_tuning;
 
 wse_status wse_get_tuning(wse_ctx* ctx, wse_tuning* tuning);
 wse_status wse_set_tuning(wse_ctx* ctx, const wse_tuning* tuning);
 /* Autotuner: estimate a seeded sample of about `sample` configurations of
  * the given spaces under candidate tunings (coordinate descent over the
- * four parameters), keep the fastest on this device, install it in the
+ * five parameters), keep the fastest on this device, install it in the
  * context and return it in *chosen. */
 wse_status wse_autotune(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces, int32_t sample,
                         wse_tuning* chosen);
@@ -272,8 +275,9 @@ wse_status wse_last_timings(const wse_ctx* ctx, double* ms, int32_t n);
 
 /* Work statistics of the last wse_estimate call on this context (n <= 8
  * entries): [0] (thread, instruction) address evaluations performed over all
- * thread sets, [1] hash-table bytes used, [2] evaluation-kernel launches,
- * [3] arena rounds, [4] configurations evaluated. */
+ * thread sets, [1] table bytes used (hash tables and bitmaps), [2]
+ * evaluation-kernel launches, [3] arena rounds, [4] configurations
+ * evaluated, [5] configurations whose sets were kept as bitmaps. */
 wse_status wse_last_stats(wse_ctx* ctx, int64_t* stats, int32_t n);
 
 /* Address evaluations the last wse_estimate call performed for each of its

@@ -220,6 +220,7 @@ struct wse_ctx {
     // tuning
     int lds_slots = 2048;
     int table_slack = 1;
+    int bitmap_log2 = 5;
     int groups_per_cu = 16;
     int64_t target_evals = 1 << 19;
     bool dirty_kernels = false, dirty_hws = false;
@@ -227,7 +228,7 @@ struct wse_ctx {
     EventPool events, round_events;
     // statistics of the last synchronous estimate
     double timings[8] = {0};
-    int64_t last_total = 0, last_table_bytes = 0, last_launches = 0, last_rounds = 0;
+    int64_t last_total = 0, last_table_bytes = 0, last_launches = 0, last_rounds = 0, last_dense = 0;
     std::vector<Counters> last_ctr;
     std::vector<int32_t> last_E;
     wse_server* server = nullptr;
@@ -737,7 +738,8 @@ static wse_status job_prepare(wse_ctx* c, Job& j, hipStream_t st)
     HIP_TRY(j.d_space_first.reserve(n_spaces + 1));
     HIP_TRY(hipMemcpyAsync(j.d_space_first.p, first.data(), first.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(j.d_cfg_space.p, cfg_space.data(), j.total * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_decode(j.d_cfgs.p, j.total, dev_tables(c, j.d_spaces.p, n_spaces), c->table_slack, st));
+    HIP_TRY(launch_decode(j.d_cfgs.p, j.total, dev_tables(c, j.d_spaces.p, n_spaces), c->table_slack,
+                          c->bitmap_log2, st));
     HIP_TRY(launch_fill_zero(j.d_ctr.p, j.total * (int64_t)sizeof(Counters), st));
     j.cfgs.resize(j.total);
     HIP_TRY(hipMemcpyAsync(j.cfgs.data(), j.d_cfgs.p, j.total * sizeof(Cfg), hipMemcpyDeviceToHost, st));
@@ -879,7 +881,7 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
         add(0, PASS_W, (g.w1 - g.w0) * spb, per);
         if (g.smin >= 0) add(1, PASS_L, (g.w0 - g.smin) * spb, per);
         for (int t = 0; t < N_TABLES; t++)
-            if (g.tab[t].log2cap > 0) add(2, t, (int64_t)1 << g.tab[t].log2cap, 1 << 16);
+            if (table_used(g.tab[t])) add(2, t, table_units(g.tab[t]), 1 << 16);
     }
     RoundDesc rd;
     std::memset(&rd, 0, sizeof(rd));
@@ -994,7 +996,11 @@ extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t 
         c->last_total = j.total;
         c->last_ctr.resize(j.total);
         c->last_E.resize(j.total);
-        for (int64_t i = 0; i < j.total; i++) c->last_E[i] = j.cfgs[i].status == 0 ? j.cfgs[i].E : 0;
+        c->last_dense = 0;
+        for (int64_t i = 0; i < j.total; i++) {
+            c->last_E[i] = j.cfgs[i].status == 0 ? j.cfgs[i].E : 0;
+            c->last_dense += j.cfgs[i].status == 0 && j.cfgs[i].dense;
+        }
         hipError_t e = hipMemcpy(c->last_ctr.data(), j.d_ctr.p, j.total * sizeof(Counters), hipMemcpyDeviceToHost);
         if (e != hipSuccess) s = fail(WSE_EDEVICE, hipGetErrorString(e));
     }
@@ -1009,7 +1015,8 @@ extern "C" wse_status wse_last_stats(wse_ctx* c, int64_t* stats, int32_t n)
     int64_t evals = 0;
     for (int64_t i = 0; i < c->last_total; i++)
         evals += (int64_t)(c->last_ctr[i].lanes_B + c->last_ctr[i].lanes_W + c->last_ctr[i].lanes_L) * c->last_E[i];
-    int64_t v[8] = {evals, c->last_table_bytes, c->last_launches, c->last_rounds, c->last_total, 0, 0, 0};
+    int64_t v[8] = {evals, c->last_table_bytes, c->last_launches, c->last_rounds, c->last_total, c->last_dense,
+                    0, 0};
     for (int i = 0; i < n && i < 8; i++) stats[i] = v[i];
     return WSE_OK;
 }
@@ -1068,6 +1075,7 @@ static wse_status check_tuning(const wse_ctx* c, const wse_tuning* t)
     if (t->table_slack_log2 < 1 || t->table_slack_log2 > 3) return fail(WSE_EINVAL, "table_slack_log2 must be 1..3");
     if (t->item_evals < (1 << 12) || t->item_evals > (1 << 22)) return fail(WSE_EINVAL, "item_evals must be 2^12..2^22");
     if (t->groups_per_cu < 1 || t->groups_per_cu > 64) return fail(WSE_EINVAL, "groups_per_cu must be 1..64");
+    if (t->bitmap_log2 < 0 || t->bitmap_log2 > 8) return fail(WSE_EINVAL, "bitmap_log2 must be 0..8");
     return WSE_OK;
 }
 
@@ -1077,7 +1085,7 @@ static void get_tuning(const wse_ctx* c, wse_tuning* t)
     t->table_slack_log2 = c->table_slack;
     t->item_evals = c->target_evals;
     t->groups_per_cu = c->groups_per_cu;
-    t->pad = 0;
+    t->bitmap_log2 = c->bitmap_log2;
 }
 
 static void put_tuning(wse_ctx* c, const wse_tuning* t)
@@ -1086,6 +1094,7 @@ static void put_tuning(wse_ctx* c, const wse_tuning* t)
     c->table_slack = t->table_slack_log2;
     c->target_evals = t->item_evals;
     c->groups_per_cu = t->groups_per_cu;
+    c->bitmap_log2 = t->bitmap_log2;
 }
 
 extern "C" wse_status wse_get_tuning(wse_ctx* c, wse_tuning* t)
@@ -1167,7 +1176,8 @@ extern "C" wse_status wse_autotune(wse_ctx* c, const wse_space* spaces, int32_t 
     const int64_t item_c[3] = {1 << 17, 1 << 19, 1 << 21};
     const int slack_c[2] = {1, 2};
     const int groups_c[3] = {8, 16, 32};
-    for (int param = 0; param < 4; param++) {
+    const int bitmap_c[3] = {0, 3, 6};
+    for (int param = 0; param < 5; param++) {
         int n_c = param == 2 ? 2 : 3;
         for (int v = 0; v < n_c; v++) {
             wse_tuning t = best;
@@ -1175,6 +1185,7 @@ extern "C" wse_status wse_autotune(wse_ctx* c, const wse_space* spaces, int32_t 
             if (param == 1) t.item_evals = item_c[v];
             if (param == 2) t.table_slack_log2 = slack_c[v];
             if (param == 3) t.groups_per_cu = groups_c[v];
+            if (param == 4) t.bitmap_log2 = bitmap_c[v];
             if (memcmp(&t, &best, sizeof(t)) == 0 || eval_lds_bytes(t.lds_slots) > c->max_lds) continue;
             put_tuning(c, &t);
             double ms = 0;

@@ -18,16 +18,30 @@ enum { MODE_SET = 0, MODE_OR = 1, MODE_MAX = 2 };
 constexpr int kLanes = 64;          // gfx950 wavefront
 constexpr int kWavesPerGroup = 4;   // evaluation workgroup = 4 independent waves
 
-// Open-addressing table of 8-byte entries ((key + 1) << pb) | payload; 0 = empty.
-// key = field * span + (unit - umin) for unit = floor(address / granularity).
+// One set of keys of a configuration, key = field * span + (unit - umin) for
+// unit = floor(address / granularity).  Two representations:
+//  - hash: open-addressing table of 8-byte entries ((key + 1) << pb) | payload,
+//    0 = empty;
+//  - bitmap (dense configurations): bit `key` of 32-bit words, one bitmap per
+//    flag or layer band (see k_decode for the layout of each table).
 struct TableDesc {
     int64_t umin;
     int64_t span;
-    int64_t off;       // byte offset of the slots in the arena (host-assigned)
-    int64_t tag_off;   // byte offset of an int32 tag per slot (W sector table), -1 if none
-    int32_t log2cap;   // capacity = 2^log2cap slots; 0 = unused
-    int32_t pb;        // payload bits
+    int64_t off;       // byte offset of the slots or bitmaps in the arena
+    int64_t tag_off;   // hash: int32 tag per slot (W sector table); bitmap: the layer
+                       // sector bands (W sector table); -1 if none
+    int64_t words;     // bitmap: 32-bit words of one bitmap; 0 for hash tables
+    int32_t log2cap;   // hash: capacity = 2^log2cap slots; 0 = unused
+    int32_t pb;        // hash: payload bits
 };
+
+// a table takes part in the configuration's passes
+__host__ __device__ inline bool table_used(const TableDesc& T) { return T.log2cap > 0 || T.words > 0; }
+// units the counting kernel scans: slots of a hash table, words of a bitmap
+__host__ __device__ inline int64_t table_units(const TableDesc& T)
+{
+    return T.words > 0 ? T.words : (T.log2cap > 0 ? (int64_t)1 << T.log2cap : 0);
+}
 
 // resident kernel
 struct KernelDev {
@@ -93,6 +107,8 @@ struct Cfg {
     int64_t P, occ, N, nbt, w0, w1, kB, smin;
     int64_t s[3];
     int32_t order[3], n_order;  // non-empty layer sets by recency
+    int32_t dense;              // tables are bitmaps (else hash tables)
+    int32_t pad2;
     int64_t sy, sz, g;
     int64_t evals[3];           // thread x instruction evaluations per pass (upper bound)
     TableDesc tab[N_TABLES];
@@ -159,7 +175,8 @@ struct ExpandJob {
 };
 
 hipError_t launch_expand(const ExpandJob* jobs_dev, int n_jobs, DevTables t, hipStream_t s);
-hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2, hipStream_t s);
+hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2, int bitmap_log2,
+                         hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 // round launches: sizes come from the device-resident RoundDesc
 hipError_t launch_round_fill(void* arena, const RoundDesc* rd, int64_t max_groups, hipStream_t s);

@@ -318,7 +318,7 @@ __device__ int64_t round_cap(int64_t bound, int slack, int* log2cap)
     return (int64_t)1 << l;
 }
 
-__global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack)
+__global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitmap_log2)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -451,11 +451,17 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack)
     int pbs[N_TABLES] = {0, 0, 2, 0, c.tag_bits};
     int64_t ev[N_TABLES] = {(int64_t)c.P * c.n_ld, (int64_t)c.P * c.n_ld, c.evals[PASS_W],
                             c.evals[PASS_W], c.evals[PASS_L]};
-    int64_t bytes = 0;
+    // key range of every table; the same validity checks hold for both
+    // representations, so that a configuration's status never depends on
+    // the tuning
+    uint64_t keys_of[N_TABLES] = {0, 0, 0, 0, 0};
+    int l2_of[N_TABLES] = {0, 0, 0, 0, 0};
+    bool dense = bitmap_log2 > 0;
     for (int q = 0; q < N_TABLES; q++) {
         TableDesc& T = c.tab[q];
         T.off = 0;
         T.tag_off = -1;
+        T.words = 0;
         T.log2cap = 0;
         T.pb = pbs[q];
         if (khi[q] <= klo[q] || klo[q] < 0 || ev[q] == 0) continue;
@@ -471,40 +477,71 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack)
             break;
         }
         int64_t bound = (int64_t)keys < ev[q] ? (int64_t)keys : ev[q];
-        int l2 = 0;
-        int64_t cap = round_cap(bound, slack, &l2);
-        if (l2 > 32) {
+        round_cap(bound, slack, &l2_of[q]);
+        if (l2_of[q] > 32) {
             bad = 2;
             break;
         }
-        T.log2cap = l2;
+        keys_of[q] = keys;
+        // a bitmap pays off when the key range is at most 2^bitmap_log2 times
+        // the evaluations that can reach it
+        if ((keys >> bitmap_log2) > (uint64_t)ev[q] || keys >= ((uint64_t)1 << 32)) dense = false;
+    }
+    // the layer pass keys its sectors with the wave table's layout and a tag
+    if (!bad && c.smin >= 0 && keys_of[T_WSEC] > 0) {
+        if (bits_for(keys_of[T_WSEC]) + c.tag_bits > 64) bad = 1;
+    }
+    if (c.tag_bits > 31) bad = 1;
+    // arena layout.  Bitmaps: B sector, B line, W line and L line tables hold
+    // one bitmap each, except that L lines hold one per layer band; the W
+    // sector table holds a load and a store bitmap, then (tag_off) one sector
+    // bitmap per layer band.  Layer band a collects blocks in
+    // [s_order[a], s_order[a-1]) with s_order[-1] = w0.
+    int64_t bytes = 0;
+    for (int q = 0; q < N_TABLES && !bad; q++) {
+        TableDesc& T = c.tab[q];
+        if (keys_of[q] == 0) continue;
         T.off = bytes;
-        bytes += cap * 8;
-        if (q == T_WSEC) {
-            T.tag_off = bytes;
-            bytes += cap * 4;
+        if (dense) {
+            T.words = (int64_t)((keys_of[q] + 31) / 32);
+            int64_t n_bm = q == T_WSEC ? 2 : (q == T_LLINE ? c.n_order : 1);
+            bytes += n_bm * T.words * 4;
+            if (q == T_WSEC && c.smin >= 0) {
+                bytes = (bytes + 255) & ~(int64_t)255;
+                T.tag_off = bytes;
+                bytes += (int64_t)c.n_order * T.words * 4;
+            }
+        } else {
+            T.log2cap = l2_of[q];
+            bytes += ((int64_t)1 << l2_of[q]) * 8;
+            if (q == T_WSEC) {
+                T.tag_off = bytes;
+                bytes += ((int64_t)1 << l2_of[q]) * 4;
+            }
         }
         bytes = (bytes + 255) & ~(int64_t)255;
     }
-    // the layer pass keys its sectors with the wave table's layout and a tag
-    if (!bad && c.smin >= 0 && c.tab[T_WSEC].log2cap > 0) {
-        uint64_t keys = (uint64_t)K.n_fields * (uint64_t)c.tab[T_WSEC].span;
-        if (bits_for(keys) + c.tag_bits > 64) bad = 1;
-    }
-    if (c.tag_bits > 31) bad = 1;
+    c.dense = dense ? 1 : 0;
     if (bad) {
         c.status = bad == 2 ? -2 : -3;
         bytes = 0;
+        c.dense = 0;
+        for (int q = 0; q < N_TABLES; q++) {
+            c.tab[q].words = 0;
+            c.tab[q].log2cap = 0;
+        }
     }
     c.table_bytes = bytes;
     cfgs[i] = c;
 }
 
-hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2, hipStream_t s)
+hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2, int bitmap_log2,
+                         hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + 127) / 128;
-    hipLaunchKernelGGL(k_decode, dim3((unsigned)blocks), dim3(128), 0, s, cfgs, n, t, table_slack_log2);
+    hipLaunchKernelGGL(k_decode, dim3((unsigned)blocks), dim3(128), 0, s, cfgs, n, t, table_slack_log2,
+                       bitmap_log2);
     return hipGetLastError();
 }
 
@@ -764,11 +801,42 @@ __device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, const Tab
 
 __device__ __forceinline__ int32_t readlane32(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// Set bit `key` of a bitmap for every lane with `act`.  Lanes of a 16-lane
+// row first merge the bits of equal words (an OR-scan over lanes whose word
+// matches, by DPP row shifts), and only the last lane of each run of equal
+// words issues the atomic, so a row of consecutive keys costs one or two
+// atomics.  Must be called by all lanes of the wave.
+__device__ __forceinline__ void bitmap_or(unsigned* bm, bool act, uint32_t key)
+{
+    const uint32_t kNone = 0xffffffffu, kEdge = 0xfffffffeu;  // never a word index (< 2^27)
+    const uint32_t w = act ? key >> 5 : kNone;
+    uint32_t bits = act ? 1u << (key & 31) : 0u;
+    uint32_t pw, pb;
+    // row_shr:1, 2, 4, 8 (lanes before the row start read kEdge / 0)
+    pw = (uint32_t)__builtin_amdgcn_update_dpp((int)kEdge, (int)w, 0x111, 0xf, 0xf, false);
+    pb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x111, 0xf, 0xf, false);
+    bits |= pw == w ? pb : 0u;
+    pw = (uint32_t)__builtin_amdgcn_update_dpp((int)kEdge, (int)w, 0x112, 0xf, 0xf, false);
+    pb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x112, 0xf, 0xf, false);
+    bits |= pw == w ? pb : 0u;
+    pw = (uint32_t)__builtin_amdgcn_update_dpp((int)kEdge, (int)w, 0x114, 0xf, 0xf, false);
+    pb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x114, 0xf, 0xf, false);
+    bits |= pw == w ? pb : 0u;
+    pw = (uint32_t)__builtin_amdgcn_update_dpp((int)kEdge, (int)w, 0x118, 0xf, 0xf, false);
+    pb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x118, 0xf, 0xf, false);
+    bits |= pw == w ? pb : 0u;
+    // row_shl:1: the next lane's word; the row's last lane reads kEdge
+    const uint32_t nw = (uint32_t)__builtin_amdgcn_update_dpp((int)kEdge, (int)w, 0x101, 0xf, 0xf, false);
+    if (act && nw != w) atomicOr(&bm[w], bits);
+}
+
 // One pass (representative block, wave or layer interval) over the segments
 // [j0, j1) of 64 consecutive threads.  The workgroup's waves take
-// consecutive segments in lockstep, one instruction per step, so that the
-// keys they share meet in the shared LDS sets.
-template <int PASS, int KIND>
+// consecutive segments, one instruction per step.  Hash configurations
+// insert into the workgroup's shared LDS sets (the waves move in lockstep so
+// that the keys they share meet there); bitmap configurations set their bits
+// in HBM directly and need no synchronisation.
+template <int PASS, int KIND, bool DENSE>
 __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, int64_t j1)
 {
     const Cfg& c = *P.c;
@@ -795,10 +863,14 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
     const int line_pb = PASS == PASS_L ? tag_bits : 0;
     const int sec_mode = PASS == PASS_W ? MODE_OR : (PASS == PASS_L ? MODE_MAX : MODE_SET);
     const int line_mode = PASS == PASS_L ? MODE_MAX : MODE_SET;
-    const bool do_sec = TS.log2cap > 0;
+    const bool do_sec = table_used(TS);
     const int64_t umin_s = TS.umin, span_s = TS.span, umin_l = TL.umin, span_l = TL.span;
     const int64_t uelem = c.uniform_elem;
     const int E = c.E;
+    // bitmaps: sector (loads; W: load, then store at +words), line
+    unsigned* bm_s = (unsigned*)(P.arena + (PASS == PASS_L ? TS.tag_off : TS.off));
+    unsigned* bm_l = (unsigned*)(P.arena + TL.off);
+    const int64_t words_s = TS.words, words_l = TL.words;
 
     for (int e0 = 0; e0 < E; e0 += kLanes) {
         const int n_in = E - e0 < kLanes ? E - e0 : kLanes;
@@ -814,6 +886,7 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
         int64_t bx = k % nb0, by = (k / nb0) % nb1, bz = k / (nb0 * nb1);
         for (int64_t jg = j0; jg < j1; jg += kWavesPerGroup) {
             const bool seg_ok = jg + P.wave < j1;
+            if (DENSE && !seg_ok) break;
             const int64_t t = (int64_t)sgi * kLanes + lane;
             const bool inb = t < Pthr;
             const int64_t tx = t & (b0 - 1), ty = (t >> lb0) & (b1 - 1), tz = t >> (lb0 + lb1);
@@ -847,7 +920,15 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
                     }
                 }
             }
+            if (DENSE && vmask == 0) continue;
             const uint64_t tag = PASS == PASS_L ? (uint64_t)(kcur - smin + 1) : 0;
+            // layer band of this segment's block (bitmaps): the first set, in
+            // recency order, whose start the block reaches
+            int band = 0;
+            if (DENSE && PASS == PASS_L)
+                while (band < c.n_order - 1 && kcur < c.s[c.order[band]]) band++;
+            unsigned* bl = bm_l + (PASS == PASS_L ? band * words_l : 0);
+            unsigned* bs = bm_s + (PASS == PASS_L ? band * words_s : 0);
             int64_t base = 0;
             if (KIND == 0) base = (gx + g) + sy * (f1 * gy + g) + sz * (f2 * gz + g);
             const int64_t ubase = uelem ? base * uelem : 0;
@@ -879,45 +960,65 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
                             bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
                             if (__ballot(valid && !ok)) P.err |= 1;
                             bool act = valid && ok;
-                            uint64_t ks = act ? (uint64_t)(us + readlane64(ic.fs, q)) : 0;
-                            uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
-                            new0 = lds_add(P, P.set0, ks, 0, MODE_SET);
-                            new1 = lds_add(P, P.set1, kl, 0, MODE_SET);
+                            if (DENSE) {
+                                bitmap_or(bs, act, (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                                bitmap_or(bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                            } else {
+                                uint64_t ks = act ? (uint64_t)(us + readlane64(ic.fs, q)) : 0;
+                                uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
+                                new0 = lds_add(P, P.set0, ks, 0, MODE_SET);
+                                new1 = lds_add(P, P.set1, kl, 0, MODE_SET);
+                            }
                         }
                     } else if (PASS == PASS_W) {
                         if (st) acc_up_st += warp_distinct(valid, sec, log2_warp);
                         bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
                         if (__ballot(valid && !ok)) P.err |= 1;
                         bool act = valid && ok;
-                        uint64_t ks =
-                            act ? (((uint64_t)(us + readlane64(ic.fs, q)) << 2) | (st ? 2u : 1u)) : 0;
-                        uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
-                        new0 = lds_add(P, P.set0, ks, sec_pb, sec_mode);
-                        new1 = lds_add(P, P.set1, kl, line_pb, line_mode);
+                        if (DENSE) {
+                            bitmap_or(bs + (st ? words_s : 0), act, (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                            bitmap_or(bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                        } else {
+                            uint64_t ks =
+                                act ? (((uint64_t)(us + readlane64(ic.fs, q)) << 2) | (st ? 2u : 1u)) : 0;
+                            uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
+                            new0 = lds_add(P, P.set0, ks, sec_pb, sec_mode);
+                            new1 = lds_add(P, P.set1, kl, line_pb, line_mode);
+                        }
                     } else {
                         bool ok = (uint64_t)ul < (uint64_t)span_l;
                         if (__ballot(valid && !ok)) P.err |= 1;
-                        uint64_t kl = (valid && ok)
-                                          ? ((((uint64_t)(ul + readlane64(ic.fl, q))) << line_pb) | tag)
-                                          : 0;
-                        new1 = lds_add(P, P.set1, kl, line_pb, line_mode);
-                        if (do_sec) {
-                            bool in = valid && (uint64_t)us < (uint64_t)span_s;
-                            uint64_t ks =
-                                in ? ((((uint64_t)(us + readlane64(ic.fs, q))) << sec_pb) | tag) : 0;
-                            new0 = lds_add(P, P.set0, ks, sec_pb, sec_mode);
+                        if (DENSE) {
+                            bitmap_or(bl, valid && ok, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                            if (do_sec) {
+                                bool in = valid && (uint64_t)us < (uint64_t)span_s;
+                                bitmap_or(bs, in, (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                            }
+                        } else {
+                            uint64_t kl = (valid && ok)
+                                              ? ((((uint64_t)(ul + readlane64(ic.fl, q))) << line_pb) | tag)
+                                              : 0;
+                            new1 = lds_add(P, P.set1, kl, line_pb, line_mode);
+                            if (do_sec) {
+                                bool in = valid && (uint64_t)us < (uint64_t)span_s;
+                                uint64_t ks =
+                                    in ? ((((uint64_t)(us + readlane64(ic.fs, q))) << sec_pb) | tag) : 0;
+                                new0 = lds_add(P, P.set0, ks, sec_pb, sec_mode);
+                            }
                         }
                     }
                 }
-                step_sync<PASS>(P, new0, new1, do_sec);
+                if (!DENSE) step_sync<PASS>(P, new0, new1, do_sec);
             }
         }
     }
-    // final flush of the item and accumulators
-    __syncthreads();
-    flush_both<PASS>(P, do_sec);
-    __syncthreads();
-    P.fill0 = P.fill1 = 0;
+    if (!DENSE) {
+        // final flush of the item's LDS sets
+        __syncthreads();
+        flush_both<PASS>(P, do_sec);
+        __syncthreads();
+        P.fill0 = P.fill1 = 0;
+    }
     if (lane == 0) {
         if (PASS == PASS_B) {
             atomicAdd(&ctr->lanes_B, (unsigned long long)acc_lanes);
@@ -987,14 +1088,27 @@ __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work
         P.fill0 = P.fill1 = 0;
         P.step = 0;
         P.err = 0;
+        const bool dense = __builtin_amdgcn_readfirstlane(c.dense) != 0;
         if (c.kind == 0) {
-            if (pass == PASS_B) run_pass<PASS_B, 0>(P, cc, c.kB, j0, j1);
-            else if (pass == PASS_W) run_pass<PASS_W, 0>(P, cc, c.w0, j0, j1);
-            else run_pass<PASS_L, 0>(P, cc, c.smin, j0, j1);
+            if (dense) {
+                if (pass == PASS_B) run_pass<PASS_B, 0, true>(P, cc, c.kB, j0, j1);
+                else if (pass == PASS_W) run_pass<PASS_W, 0, true>(P, cc, c.w0, j0, j1);
+                else run_pass<PASS_L, 0, true>(P, cc, c.smin, j0, j1);
+            } else {
+                if (pass == PASS_B) run_pass<PASS_B, 0, false>(P, cc, c.kB, j0, j1);
+                else if (pass == PASS_W) run_pass<PASS_W, 0, false>(P, cc, c.w0, j0, j1);
+                else run_pass<PASS_L, 0, false>(P, cc, c.smin, j0, j1);
+            }
         } else {
-            if (pass == PASS_B) run_pass<PASS_B, 1>(P, cc, c.kB, j0, j1);
-            else if (pass == PASS_W) run_pass<PASS_W, 1>(P, cc, c.w0, j0, j1);
-            else run_pass<PASS_L, 1>(P, cc, c.smin, j0, j1);
+            if (dense) {
+                if (pass == PASS_B) run_pass<PASS_B, 1, true>(P, cc, c.kB, j0, j1);
+                else if (pass == PASS_W) run_pass<PASS_W, 1, true>(P, cc, c.w0, j0, j1);
+                else run_pass<PASS_L, 1, true>(P, cc, c.smin, j0, j1);
+            } else {
+                if (pass == PASS_B) run_pass<PASS_B, 1, false>(P, cc, c.kB, j0, j1);
+                else if (pass == PASS_W) run_pass<PASS_W, 1, false>(P, cc, c.w0, j0, j1);
+                else run_pass<PASS_L, 1, false>(P, cc, c.smin, j0, j1);
+            }
         }
     }
 }
@@ -1034,9 +1148,51 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
     int64_t i0 = local * W->per_item;
     int64_t i1 = i0 + W->per_item < W->n_units ? i0 + W->per_item : W->n_units;
     int64_t n0 = 0, n1 = 0, sh[3] = {0, 0, 0}, ll[3] = {0, 0, 0};
-    const unsigned* tags = q == T_WSEC ? (const unsigned*)(arena + T.tag_off) : nullptr;
+    if (T.words > 0) {
+        // bitmaps: popcounts, and the layer bands in recency order
+        const unsigned* bm = (const unsigned*)(arena + T.off);
+        const int64_t nw = T.words;
+        const int n_bands = c.n_order;
+        const unsigned* bands = q == T_WSEC && T.tag_off >= 0 ? (const unsigned*)(arena + T.tag_off) : nullptr;
+        for (int64_t i = i0 + lane; i < i1; i += kLanes) {
+            if (q == T_WSEC) {
+                const unsigned ld = bm[i];
+                n0 += __popc(ld);
+                n1 += __popc(bm[nw + i]);
+                if (bands) {
+                    unsigned acc = 0;
+#pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        if (a >= n_bands) break;
+                        const unsigned cur = bands[a * nw + i];
+                        const int v = __popc(ld & cur & ~acc);
+                        acc |= cur;
+                        const int d = c.order[a];
+                        sh[0] += d == 0 ? v : 0;
+                        sh[1] += d == 1 ? v : 0;
+                        sh[2] += d == 2 ? v : 0;
+                    }
+                }
+            } else if (q == T_LLINE) {
+                unsigned acc = 0;
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    if (a >= n_bands) break;
+                    acc |= bm[a * nw + i];
+                    const int v = __popc(acc);
+                    const int d = c.order[a];
+                    ll[0] += d == 0 ? v : 0;
+                    ll[1] += d == 1 ? v : 0;
+                    ll[2] += d == 2 ? v : 0;
+                }
+            } else {
+                n0 += __popc(bm[i]);
+            }
+        }
+    }
+    const unsigned* tags = q == T_WSEC && T.words == 0 ? (const unsigned*)(arena + T.tag_off) : nullptr;
     uint64_t pmask = ((uint64_t)1 << T.pb) - 1;
-    for (int64_t i = i0 + lane; i < i1; i += kLanes) {
+    for (int64_t i = i0 + lane; i < i1 && T.words == 0; i += kLanes) {
         unsigned long long e = slots[i];
         if (e == 0) continue;
         if (q == T_WSEC) {

@@ -78,7 +78,7 @@ class wse_space(C.Structure):
 
 class wse_tuning(C.Structure):
     _fields_ = [("lds_slots", C.c_int32), ("table_slack_log2", C.c_int32),
-                ("item_evals", C.c_int64), ("groups_per_cu", C.c_int32), ("pad", C.c_int32)]
+                ("item_evals", C.c_int64), ("groups_per_cu", C.c_int32), ("bitmap_log2", C.c_int32)]
 
 
 class wse_server_opts(C.Structure):
@@ -331,11 +331,12 @@ class Context:
         return r
 
     def last_stats(self):
-        """dict of the last call's work: evaluations, table bytes, launches, rounds, configs"""
+        """dict of the last call's work: evaluations, table bytes, launches, rounds, configs,
+        configurations kept as bitmaps"""
         v = (C.c_int64 * 8)()
         _check(lib().wse_last_stats(self._ctx, v, 8), self._ctx)
         return {"evals": v[0], "table_bytes": v[1], "eval_launches": v[2], "rounds": v[3],
-                "configs": v[4]}
+                "configs": v[4], "bitmap_configs": v[5]}
 
     def last_evals(self, n):
         """address evaluations of each configuration of the last call"""
@@ -347,13 +348,14 @@ class Context:
         t = wse_tuning()
         _check(lib().wse_get_tuning(self._ctx, C.byref(t)), self._ctx)
         return {"lds_slots": t.lds_slots, "table_slack_log2": t.table_slack_log2,
-                "item_evals": t.item_evals, "groups_per_cu": t.groups_per_cu}
+                "item_evals": t.item_evals, "groups_per_cu": t.groups_per_cu,
+                "bitmap_log2": t.bitmap_log2}
 
     def set_tuning(self, **kw):
         cur = self.tuning()
         cur.update(kw)
         t = wse_tuning(cur["lds_slots"], cur["table_slack_log2"], cur["item_evals"],
-                       cur["groups_per_cu"], 0)
+                       cur["groups_per_cu"], cur["bitmap_log2"])
         _check(lib().wse_set_tuning(self._ctx, C.byref(t)), self._ctx)
 
     def autotune(self, specs, sample=32):
@@ -362,7 +364,8 @@ class Context:
         t = wse_tuning()
         _check(lib().wse_autotune(self._ctx, arr, len(specs), int(sample), C.byref(t)), self._ctx)
         return {"lds_slots": t.lds_slots, "table_slack_log2": t.table_slack_log2,
-                "item_evals": t.item_evals, "groups_per_cu": t.groups_per_cu}
+                "item_evals": t.item_evals, "groups_per_cu": t.groups_per_cu,
+                "bitmap_log2": t.bitmap_log2}
 
     def last_timings(self):
         t = (C.c_double * 8)()

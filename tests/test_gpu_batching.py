@@ -88,9 +88,9 @@ def test_results_do_not_depend_on_tuning(small_ctx):
     say("case batching: tunings")
     ref, rrank = small_ctx.estimate(reg, mode=wsest.BATCHED)
     try:
-        for t in [dict(lds_slots=1024, item_evals=1 << 12, groups_per_cu=1),
-                  dict(lds_slots=4096, item_evals=1 << 22, table_slack_log2=3, groups_per_cu=32),
-                  dict(lds_slots=2048, item_evals=1 << 15, table_slack_log2=2, groups_per_cu=8)]:
+        for t in [dict(lds_slots=1024, item_evals=1 << 12, groups_per_cu=1, bitmap_log2=0),
+                  dict(lds_slots=4096, item_evals=1 << 22, table_slack_log2=3, groups_per_cu=32, bitmap_log2=8),
+                  dict(lds_slots=2048, item_evals=1 << 15, table_slack_log2=2, groups_per_cu=8, bitmap_log2=2)]:
             small_ctx.set_tuning(**t)
             got, grank = small_ctx.estimate(reg, mode=wsest.BATCHED)
             assert got.tobytes() == ref.tobytes(), t
@@ -121,3 +121,5 @@ def test_invalid_tuning_is_rejected(small_ctx):
         small_ctx.set_tuning(lds_slots=512)
     with pytest.raises(wsest.WseError):
         small_ctx.set_tuning(groups_per_cu=0)
+    with pytest.raises(wsest.WseError):
+        small_ctx.set_tuning(bitmap_log2=9)

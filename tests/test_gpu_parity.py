@@ -23,12 +23,16 @@ def say(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def ctx():
+# every parity case runs with the sets kept as bitmaps wherever the key
+# ranges allow it, and again with hash tables only
+@pytest.fixture(scope="module", params=["bitmap", "hash"])
+def ctx(request):
     if not gpu_available():
         pytest.skip("no GPU")
     from paper_2204_14242_amd import wsest
     c = wsest.Context(0, arena_bytes=8 << 30)
+    c.set_tuning(bitmap_log2=8 if request.param == "bitmap" else 0)
+    c.representation = request.param
     yield c
     c.close()
 
@@ -56,7 +60,11 @@ def test_rhat_bitwise(ctx, orc):
 def test_stencil_64_sample(ctx, orc):
     k, hw, sp = W.stencil_plain()
     sp = dict(sp, domains=[(64, 64, 64)], explicit=list(range(0, 230, 7)))
-    check(ctx, orc, [(k, hw, sp)], "stencil 64^3")
+    got = check(ctx, orc, [(k, hw, sp)], "stencil 64^3")
+    # the representation asked for is the one that ran
+    n_bitmap = ctx.last_stats()["bitmap_configs"]
+    n_ok = int((got["status"] == 0).sum())
+    assert n_bitmap == (n_ok if ctx.representation == "bitmap" else 0)
 
 
 def test_stencil_folding_and_elements(ctx, orc):
