@@ -205,8 +205,9 @@ typedef struct {
     int32_t table_slack_log2;   /* HBM hash tables hold at least 2^slack slots per key bound (1..3) */
     int64_t item_evals;         /* address evaluations per work item of a workgroup (2^12 .. 2^22) */
     int32_t groups_per_cu;      /* resident-loop workgroups per compute unit (1 .. 64) */
-    int32_t bitmap_log2;        /* a configuration keeps its sets as bitmaps instead of hash tables
-                                   when every set's key range is at most 2^bitmap_log2 times the
+    int32_t bitmap_log2;        /* the block pass's sets, and the wave and layer passes' sets, are
+                                   kept as bitmaps instead of hash tables when every set of the
+                                   group has a key range of at most 2^bitmap_log2 times the
                                    evaluations that reach it (and below 2^32 keys); 0 = always
                                    hash tables (0 .. 8) */
 } wse_tuning;
@@ -277,7 +278,7 @@ wse_status wse_last_timings(const wse_ctx* ctx, double* ms, int32_t n);
  * entries): [0] (thread, instruction) address evaluations performed over all
  * thread sets, [1] table bytes used (hash tables and bitmaps), [2]
  * evaluation-kernel launches, [3] arena rounds, [4] configurations
- * evaluated, [5] configurations whose sets were kept as bitmaps. */
+ * evaluated, [5] configurations with sets kept as bitmaps. */
 wse_status wse_last_stats(wse_ctx* ctx, int64_t* stats, int32_t n);
 
 /* Address evaluations the last wse_estimate call performed for each of its

@@ -999,7 +999,7 @@ extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t 
         c->last_dense = 0;
         for (int64_t i = 0; i < j.total; i++) {
             c->last_E[i] = j.cfgs[i].status == 0 ? j.cfgs[i].E : 0;
-            c->last_dense += j.cfgs[i].status == 0 && j.cfgs[i].dense;
+            c->last_dense += j.cfgs[i].status == 0 && j.cfgs[i].dense != 0;
         }
         hipError_t e = hipMemcpy(c->last_ctr.data(), j.d_ctr.p, j.total * sizeof(Counters), hipMemcpyDeviceToHost);
         if (e != hipSuccess) s = fail(WSE_EDEVICE, hipGetErrorString(e));

@@ -112,6 +112,36 @@ __device__ __forceinline__ int set_insert(unsigned long long* slots, int log2cap
     return -1;
 }
 
+// Insert into an HBM table shared by many workgroups.  Same contract as
+// set_insert, but a slot is read before any atomic: entries only ever go
+// from empty to a key whose payload grows, so a stale read that shows the
+// key with the payload already covered needs no atomic at all, and any other
+// stale read is settled by the compare-and-swap or the merge.
+__device__ __forceinline__ int table_insert(unsigned long long* slots, int log2cap, uint64_t entry, int pb,
+                                            int mode)
+{
+    const uint64_t key1 = entry >> pb;
+    const uint32_t mask = (uint32_t)(((uint64_t)1 << log2cap) - 1);
+    uint32_t pos = slot_of(key1, log2cap);
+    for (uint64_t probe = 0; probe <= mask; probe++) {
+        unsigned long long cur = __hip_atomic_load(&slots[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (cur == 0) {
+            cur = atomicCAS(&slots[pos], 0ull, (unsigned long long)entry);
+            if (cur == 0) return 1;
+        }
+        if ((cur >> pb) == key1) {
+            if (mode == MODE_MAX) {
+                if (entry > cur) atomicMax(&slots[pos], (unsigned long long)entry);
+            } else if (mode == MODE_OR) {
+                if ((cur | entry) != cur) atomicOr(&slots[pos], (unsigned long long)entry);
+            }
+            return 0;
+        }
+        pos = (pos + 1) & mask;
+    }
+    return -1;
+}
+
 // position of key1 in a global table, -1 if absent
 __device__ __forceinline__ int64_t set_find(const unsigned long long* slots, int log2cap, uint64_t key1,
                                             int pb)
@@ -456,7 +486,9 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
     // the tuning
     uint64_t keys_of[N_TABLES] = {0, 0, 0, 0, 0};
     int l2_of[N_TABLES] = {0, 0, 0, 0, 0};
-    bool dense = bitmap_log2 > 0;
+    // representation per group of tables: the block pass's (B sectors and
+    // lines) and the wave and layer passes' (W sectors, W lines, L lines)
+    bool dense_g[2] = {bitmap_log2 > 0, bitmap_log2 > 0};
     for (int q = 0; q < N_TABLES; q++) {
         TableDesc& T = c.tab[q];
         T.off = 0;
@@ -485,7 +517,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         keys_of[q] = keys;
         // a bitmap pays off when the key range is at most 2^bitmap_log2 times
         // the evaluations that can reach it
-        if ((keys >> bitmap_log2) > (uint64_t)ev[q] || keys >= ((uint64_t)1 << 32)) dense = false;
+        if ((keys >> bitmap_log2) > (uint64_t)ev[q] || keys >= ((uint64_t)1 << 32)) dense_g[q >= T_WSEC] = false;
     }
     // the layer pass keys its sectors with the wave table's layout and a tag
     if (!bad && c.smin >= 0 && keys_of[T_WSEC] > 0) {
@@ -497,12 +529,24 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
     // sector table holds a load and a store bitmap, then (tag_off) one sector
     // bitmap per layer band.  Layer band a collects blocks in
     // [s_order[a], s_order[a-1]) with s_order[-1] = w0.
+    // (bitmap words are addressed by 32-bit offsets: a layout of 2^33 bytes
+    // or more falls back to hash tables)
     int64_t bytes = 0;
     for (int q = 0; q < N_TABLES && !bad; q++) {
         TableDesc& T = c.tab[q];
+        if (q == 0 && (dense_g[0] || dense_g[1])) {
+            // upper bound of the layout's bytes
+            int64_t need = 0;
+            for (int r = 0; r < N_TABLES; r++) {
+                int64_t w = (int64_t)((keys_of[r] + 31) / 32);
+                int64_t n_bm = r == T_WSEC ? 2 + (c.smin >= 0 ? c.n_order : 0) : (r == T_LLINE ? c.n_order : 1);
+                need += dense_g[r >= T_WSEC] ? n_bm * w * 4 + 512 : ((int64_t)12 << l2_of[r]) + 512;
+            }
+            if (need >= ((int64_t)1 << 33)) dense_g[0] = dense_g[1] = false;
+        }
         if (keys_of[q] == 0) continue;
         T.off = bytes;
-        if (dense) {
+        if (dense_g[q >= T_WSEC]) {
             T.words = (int64_t)((keys_of[q] + 31) / 32);
             int64_t n_bm = q == T_WSEC ? 2 : (q == T_LLINE ? c.n_order : 1);
             bytes += n_bm * T.words * 4;
@@ -521,7 +565,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         }
         bytes = (bytes + 255) & ~(int64_t)255;
     }
-    c.dense = dense ? 1 : 0;
+    c.dense = (dense_g[0] ? 1 : 0) | (dense_g[1] ? 2 : 0);
     if (bad) {
         c.status = bad == 2 ? -2 : -3;
         bytes = 0;
@@ -669,6 +713,12 @@ struct PassCtx {
     int fill0, fill1;          // running fills of the sets, the same in every wave
     int step;
     uint64_t err;
+    // bitmap configurations: this wave's LDS table of bitmap words, keyed by
+    // the word's offset in the configuration's tables (+1; 0 = empty)
+    uint32_t* wkey;
+    uint32_t* wbits;
+    int wlog;                  // 2^wlog entries
+    int wfill;                 // entries in use (uniform)
 };
 
 // Move every entry of a shared LDS set into the configuration's HBM table;
@@ -684,7 +734,7 @@ __device__ void flush_set(PassCtx& P, unsigned long long* set, int q, int mode, 
         if (e == 0) continue;
         set[i] = 0;
         if (!probe_wsec) {
-            if (set_insert(slots, T.log2cap, e, T.pb, mode) < 0) overflow = true;
+            if (table_insert(slots, T.log2cap, e, T.pb, mode) < 0) overflow = true;
         } else {
             // layer sector with its block tag, probed in the wave sector table
             int tb = P.c->tag_bits;
@@ -801,33 +851,68 @@ __device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, const Tab
 
 __device__ __forceinline__ int32_t readlane32(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
-// Set bit `key` of a bitmap for every lane with `act`.  Lanes of a 16-lane
-// row first merge the bits of equal words (an OR-scan over lanes whose word
-// matches, by DPP row shifts), and only the last lane of each run of equal
-// words issues the atomic, so a row of consecutive keys costs one or two
-// atomics.  Must be called by all lanes of the wave.
-__device__ __forceinline__ void bitmap_or(unsigned* bm, bool act, uint32_t key)
+// Move this wave's LDS table of bitmap words into the configuration's
+// bitmaps in HBM (one atomic OR per word) and clear it.
+__device__ __forceinline__ void flush_words(PassCtx& P)
 {
-    const uint32_t kNone = 0xffffffffu, kEdge = 0xfffffffeu;  // never a word index (< 2^27)
-    const uint32_t w = act ? key >> 5 : kNone;
+    unsigned* words = (unsigned*)P.arena;
+    const int n = 1 << P.wlog;
+    for (int i = lane_id(); i < n; i += kLanes) {
+        const uint32_t k = P.wkey[i];
+        if (k == 0) continue;
+        const uint32_t b = P.wbits[i];
+        P.wkey[i] = 0;
+        P.wbits[i] = 0;
+        atomicOr(&words[k - 1], b);
+    }
+    wave_fence();
+    P.wfill = 0;
+}
+
+// Set bit `key` of the bitmap at word offset `base` of the configuration's
+// tables, for every lane with `act`.  Lanes of a 16-lane row first merge the
+// bits of equal words (an OR-scan over lanes whose word matches, by DPP row
+// shifts); the last lane of each run of equal words ORs the merged bits into
+// the wave's LDS table of words, which reaches HBM when it is flushed.
+// Must be called by all lanes of the wave.  Returns the entries it added.
+__device__ __forceinline__ int bitmap_or(PassCtx& P, uint32_t base, bool act, uint32_t key)
+{
+    // word index + 1 (< 2^27); lanes without a key hold a value no word has,
+    // and lanes past a row edge read 0 from the DPP moves (bound_ctrl)
+    const uint32_t w1 = act ? (key >> 5) + 1 : 0xffffffffu;
     uint32_t bits = act ? 1u << (key & 31) : 0u;
-    uint32_t pw, pb;
-    // row_shr:1, 2, 4, 8 (lanes before the row start read kEdge / 0)
-    pw = (uint32_t)__builtin_amdgcn_update_dpp((int)kEdge, (int)w, 0x111, 0xf, 0xf, false);
-    pb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x111, 0xf, 0xf, false);
-    bits |= pw == w ? pb : 0u;
-    pw = (uint32_t)__builtin_amdgcn_update_dpp((int)kEdge, (int)w, 0x112, 0xf, 0xf, false);
-    pb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x112, 0xf, 0xf, false);
-    bits |= pw == w ? pb : 0u;
-    pw = (uint32_t)__builtin_amdgcn_update_dpp((int)kEdge, (int)w, 0x114, 0xf, 0xf, false);
-    pb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x114, 0xf, 0xf, false);
-    bits |= pw == w ? pb : 0u;
-    pw = (uint32_t)__builtin_amdgcn_update_dpp((int)kEdge, (int)w, 0x118, 0xf, 0xf, false);
-    pb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x118, 0xf, 0xf, false);
-    bits |= pw == w ? pb : 0u;
-    // row_shl:1: the next lane's word; the row's last lane reads kEdge
-    const uint32_t nw = (uint32_t)__builtin_amdgcn_update_dpp((int)kEdge, (int)w, 0x101, 0xf, 0xf, false);
-    if (act && nw != w) atomicOr(&bm[w], bits);
+    // row_shr:1, 2, 4, 8: inclusive OR-scan over lanes of equal word
+    bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x111, 0xf, 0xf, true) &
+            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x111, 0xf, 0xf, true) == w1));
+    bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x112, 0xf, 0xf, true) &
+            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x112, 0xf, 0xf, true) == w1));
+    bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x114, 0xf, 0xf, true) &
+            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x114, 0xf, 0xf, true) == w1));
+    bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x118, 0xf, 0xf, true) &
+            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x118, 0xf, 0xf, true) == w1));
+    // row_shl:1: the next lane's word (0 past the row's last lane)
+    const uint32_t nw1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x101, 0xf, 0xf, true);
+    const uint32_t w = w1 - 1;
+    bool added = false;
+    if (act && nw1 != w1) {
+        const uint32_t k1 = base + w + 1;
+        const uint32_t mask = (1u << P.wlog) - 1;
+        uint32_t pos = (k1 * 0x9e3779b1u) >> (32 - P.wlog);
+        // the table is at most half full: a free or matching entry exists
+        for (;;) {
+            uint32_t cur = P.wkey[pos];
+            if (cur == 0) {
+                cur = atomicCAS(&P.wkey[pos], 0u, k1);
+                if (cur == 0) added = true;
+            }
+            if (cur == 0 || cur == k1) {
+                atomicOr(&P.wbits[pos], bits);
+                break;
+            }
+            pos = (pos + 1) & mask;
+        }
+    }
+    return __popcll(__ballot(added));
 }
 
 // One pass (representative block, wave or layer interval) over the segments
@@ -837,7 +922,7 @@ __device__ __forceinline__ void bitmap_or(unsigned* bm, bool act, uint32_t key)
 // that the keys they share meet there); bitmap configurations set their bits
 // in HBM directly and need no synchronisation.
 template <int PASS, int KIND, bool DENSE>
-__device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, int64_t j1)
+__device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, int64_t j1)
 {
     const Cfg& c = *P.c;
     const int lane = lane_id();
@@ -867,10 +952,12 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
     const int64_t umin_s = TS.umin, span_s = TS.span, umin_l = TL.umin, span_l = TL.span;
     const int64_t uelem = c.uniform_elem;
     const int E = c.E;
-    // bitmaps: sector (loads; W: load, then store at +words), line
-    unsigned* bm_s = (unsigned*)(P.arena + (PASS == PASS_L ? TS.tag_off : TS.off));
-    unsigned* bm_l = (unsigned*)(P.arena + TL.off);
-    const int64_t words_s = TS.words, words_l = TL.words;
+    // bitmaps, as word offsets in the configuration's tables: sector (loads;
+    // W: load, then store at +words; L: the layer bands), line (L: bands)
+    const uint32_t off_s = (uint32_t)((PASS == PASS_L ? TS.tag_off : TS.off) >> 2);
+    const uint32_t off_l = (uint32_t)(TL.off >> 2);
+    const uint32_t words_s = (uint32_t)TS.words, words_l = (uint32_t)TL.words;
+    const int wflush = (1 << (P.wlog - 1)) - 2 * kLanes;  // flush before a step could pass half
 
     for (int e0 = 0; e0 < E; e0 += kLanes) {
         const int n_in = E - e0 < kLanes ? E - e0 : kLanes;
@@ -879,14 +966,19 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
         else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}};
         const int32_t meta = ic.st | (ic.elem << 1);
 
+        // hash configurations: the waves interleave segments in lockstep;
+        // bitmap configurations: each wave takes a contiguous quarter
+        const int64_t quarter = (j1 - j0 + kWavesPerGroup - 1) / kWavesPerGroup;
+        const int64_t ja = DENSE ? (j0 + P.wave * quarter < j1 ? j0 + P.wave * quarter : j1) : j0;
+        const int64_t jb = DENSE ? (ja + quarter < j1 ? ja + quarter : j1) : j1;
+        const int jstep = DENSE ? 1 : kWavesPerGroup;
         // this wave's first segment: block k, segment sgi, block coordinates
-        int64_t jw = j0 + P.wave;
+        int64_t jw = DENSE ? ja : j0 + P.wave;
         int64_t k = k_lo + jw / spb;
         int sgi = (int)(jw % spb);
         int64_t bx = k % nb0, by = (k / nb0) % nb1, bz = k / (nb0 * nb1);
-        for (int64_t jg = j0; jg < j1; jg += kWavesPerGroup) {
-            const bool seg_ok = jg + P.wave < j1;
-            if (DENSE && !seg_ok) break;
+        for (int64_t jg = ja; jg < jb; jg += jstep) {
+            const bool seg_ok = DENSE || jg + P.wave < j1;
             const int64_t t = (int64_t)sgi * kLanes + lane;
             const bool inb = t < Pthr;
             const int64_t tx = t & (b0 - 1), ty = (t >> lb0) & (b1 - 1), tz = t >> (lb0 + lb1);
@@ -896,8 +988,8 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
             const int64_t kcur = k;
             const int64_t bcur[3] = {bx, by, bz};
             const int64_t tcur[3] = {tx, ty, tz};
-            // advance by one segment per wave of the workgroup
-            for (int step = 0; step < kWavesPerGroup; step++) {
+            // advance to the wave's next segment
+            for (int step = 0; step < jstep; step++) {
                 if (++sgi == spb) {
                     sgi = 0;
                     k++;
@@ -927,8 +1019,8 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
             int band = 0;
             if (DENSE && PASS == PASS_L)
                 while (band < c.n_order - 1 && kcur < c.s[c.order[band]]) band++;
-            unsigned* bl = bm_l + (PASS == PASS_L ? band * words_l : 0);
-            unsigned* bs = bm_s + (PASS == PASS_L ? band * words_s : 0);
+            const uint32_t bl = off_l + (PASS == PASS_L ? (uint32_t)band * words_l : 0u);
+            const uint32_t bs = off_s + (PASS == PASS_L ? (uint32_t)band * words_s : 0u);
             int64_t base = 0;
             if (KIND == 0) base = (gx + g) + sy * (f1 * gy + g) + sz * (f2 * gz + g);
             const int64_t ubase = uelem ? base * uelem : 0;
@@ -961,8 +1053,8 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
                             if (__ballot(valid && !ok)) P.err |= 1;
                             bool act = valid && ok;
                             if (DENSE) {
-                                bitmap_or(bs, act, (uint32_t)(us + readlane64(ic.fs, q) - 1));
-                                bitmap_or(bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                                new0 = bitmap_or(P, bs, act, (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                                new1 = bitmap_or(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
                             } else {
                                 uint64_t ks = act ? (uint64_t)(us + readlane64(ic.fs, q)) : 0;
                                 uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
@@ -976,8 +1068,9 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
                         if (__ballot(valid && !ok)) P.err |= 1;
                         bool act = valid && ok;
                         if (DENSE) {
-                            bitmap_or(bs + (st ? words_s : 0), act, (uint32_t)(us + readlane64(ic.fs, q) - 1));
-                            bitmap_or(bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                            new0 = bitmap_or(P, bs + (st ? words_s : 0u), act,
+                                             (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                            new1 = bitmap_or(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
                         } else {
                             uint64_t ks =
                                 act ? (((uint64_t)(us + readlane64(ic.fs, q)) << 2) | (st ? 2u : 1u)) : 0;
@@ -989,10 +1082,10 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
                         bool ok = (uint64_t)ul < (uint64_t)span_l;
                         if (__ballot(valid && !ok)) P.err |= 1;
                         if (DENSE) {
-                            bitmap_or(bl, valid && ok, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                            new1 = bitmap_or(P, bl, valid && ok, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
                             if (do_sec) {
                                 bool in = valid && (uint64_t)us < (uint64_t)span_s;
-                                bitmap_or(bs, in, (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                                new0 = bitmap_or(P, bs, in, (uint32_t)(us + readlane64(ic.fs, q) - 1));
                             }
                         } else {
                             uint64_t kl = (valid && ok)
@@ -1008,11 +1101,21 @@ __device__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, in
                         }
                     }
                 }
-                if (!DENSE) step_sync<PASS>(P, new0, new1, do_sec);
+                if (DENSE) {
+                    P.wfill += new0 + new1;
+                    if (P.wfill > wflush) flush_words(P);
+                } else {
+                    step_sync<PASS>(P, new0, new1, do_sec);
+                }
             }
         }
     }
-    if (!DENSE) {
+    if (DENSE) {
+        // final flush of the wave's words; then no wave may start on the next
+        // item (whose LDS use may differ) before all have flushed
+        flush_words(P);
+        __syncthreads();
+    } else {
         // final flush of the item's LDS sets
         __syncthreads();
         flush_both<PASS>(P, do_sec);
@@ -1088,7 +1191,12 @@ __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work
         P.fill0 = P.fill1 = 0;
         P.step = 0;
         P.err = 0;
-        const bool dense = __builtin_amdgcn_readfirstlane(c.dense) != 0;
+        P.wkey = (uint32_t*)lds + (size_t)wave * lds_slots;
+        P.wbits = P.wkey + lds_slots / 2;
+        P.wlog = llog - 1;
+        P.wfill = 0;
+        const int dense_bits = __builtin_amdgcn_readfirstlane(c.dense);
+        const bool dense = (dense_bits & (pass == PASS_B ? 1 : 2)) != 0;
         if (c.kind == 0) {
             if (dense) {
                 if (pass == PASS_B) run_pass<PASS_B, 0, true>(P, cc, c.kB, j0, j1);
