@@ -713,12 +713,11 @@ struct PassCtx {
     int fill0, fill1;          // running fills of the sets, the same in every wave
     int step;
     uint64_t err;
-    // bitmap configurations: this wave's LDS table of bitmap words, keyed by
-    // the word's offset in the configuration's tables (+1; 0 = empty)
-    uint32_t* wkey;
-    uint32_t* wbits;
+    // bitmap configurations: this wave's direct-mapped LDS cache of bitmap
+    // words, entries ((offset + 1) << 32) | bits for the word at `offset` in
+    // the configuration's tables; 0 = empty
+    unsigned long long* wtab;
     int wlog;                  // 2^wlog entries
-    int wfill;                 // entries in use (uniform)
 };
 
 // Move every entry of a shared LDS set into the configuration's HBM table;
@@ -851,37 +850,44 @@ __device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, const Tab
 
 __device__ __forceinline__ int32_t readlane32(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
-// Move this wave's LDS table of bitmap words into the configuration's
-// bitmaps in HBM (one atomic OR per word) and clear it.
+// Move this wave's cache of bitmap words into the configuration's bitmaps in
+// HBM (one atomic OR per word) and clear it.
 __device__ __forceinline__ void flush_words(PassCtx& P)
 {
     unsigned* words = (unsigned*)P.arena;
     const int n = 1 << P.wlog;
     for (int i = lane_id(); i < n; i += kLanes) {
-        const uint32_t k = P.wkey[i];
-        if (k == 0) continue;
-        const uint32_t b = P.wbits[i];
-        P.wkey[i] = 0;
-        P.wbits[i] = 0;
-        atomicOr(&words[k - 1], b);
+        const unsigned long long e = P.wtab[i];
+        if (e == 0) continue;
+        P.wtab[i] = 0;
+        atomicOr(&words[(uint32_t)(e >> 32) - 1], (uint32_t)e);
     }
     wave_fence();
-    P.wfill = 0;
 }
 
-// Set bit `key` of the bitmap at word offset `base` of the configuration's
-// tables, for every lane with `act`.  Lanes of a 16-lane row first merge the
-// bits of equal words (an OR-scan over lanes whose word matches, by DPP row
-// shifts); the last lane of each run of equal words ORs the merged bits into
-// the wave's LDS table of words, which reaches HBM when it is flushed.
-// Must be called by all lanes of the wave.  Returns the entries it added.
-__device__ __forceinline__ int bitmap_or(PassCtx& P, uint32_t base, bool act, uint32_t key)
+// One lane's pending update of a bitmap word: the merged bits of its run of
+// equal words, the word's cache slot and the slot's content when read.
+struct WordProbe {
+    unsigned long long old;
+    uint32_t k1;      // word offset + 1; 0 = this lane has nothing to write
+    uint32_t bits;
+    uint32_t slot;
+};
+
+// First half of setting bit `key` of the bitmap at word offset `base` for
+// every lane with `act`: lanes merge the bits of equal words across the
+// wave (an OR-scan over lanes whose word matches: DPP row shifts 1, 2, 4, 8
+// within rows of 16 lanes, then the last lane of rows 0 and 2 into rows 1
+// and 3, and lane 31 into rows 2 and 3), the last lane of each run of equal
+// words keeps the update, and every lane reads its cache slot.  Must be
+// called by all lanes of the wave.
+__device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base, bool act, uint32_t key)
 {
-    // word index + 1 (< 2^27); lanes without a key hold a value no word has,
-    // and lanes past a row edge read 0 from the DPP moves (bound_ctrl)
+    // word index + 1 (< 2^27); lanes without a key hold a value no word
+    // has, and lanes whose DPP source lies outside the wave, row or row
+    // mask read 0
     const uint32_t w1 = act ? (key >> 5) + 1 : 0xffffffffu;
     uint32_t bits = act ? 1u << (key & 31) : 0u;
-    // row_shr:1, 2, 4, 8: inclusive OR-scan over lanes of equal word
     bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x111, 0xf, 0xf, true) &
             (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x111, 0xf, 0xf, true) == w1));
     bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x112, 0xf, 0xf, true) &
@@ -890,29 +896,48 @@ __device__ __forceinline__ int bitmap_or(PassCtx& P, uint32_t base, bool act, ui
             (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x114, 0xf, 0xf, true) == w1));
     bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x118, 0xf, 0xf, true) &
             (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x118, 0xf, 0xf, true) == w1));
-    // row_shl:1: the next lane's word (0 past the row's last lane)
-    const uint32_t nw1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x101, 0xf, 0xf, true);
-    const uint32_t w = w1 - 1;
-    bool added = false;
-    if (act && nw1 != w1) {
-        const uint32_t k1 = base + w + 1;
-        const uint32_t mask = (1u << P.wlog) - 1;
-        uint32_t pos = (k1 * 0x9e3779b1u) >> (32 - P.wlog);
-        // the table is at most half full: a free or matching entry exists
-        for (;;) {
-            uint32_t cur = P.wkey[pos];
-            if (cur == 0) {
-                cur = atomicCAS(&P.wkey[pos], 0u, k1);
-                if (cur == 0) added = true;
-            }
-            if (cur == 0 || cur == k1) {
-                atomicOr(&P.wbits[pos], bits);
-                break;
-            }
-            pos = (pos + 1) & mask;
+    // row_bcast:15 into rows 1 and 3, then row_bcast:31 into rows 2 and 3
+    // (other rows keep the 0 of `old`)
+    bits |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x142, 0xa, 0xf, false) &
+            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_update_dpp(0, (int)w1, 0x142, 0xa, 0xf, false) == w1));
+    bits |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x143, 0xc, 0xf, false) &
+            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_update_dpp(0, (int)w1, 0x143, 0xc, 0xf, false) == w1));
+    // wave_shl:1: the next lane's word (0 past lane 63)
+    const uint32_t nw1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x130, 0xf, 0xf, true);
+    WordProbe r;
+    const bool lead = act && nw1 != w1;
+    r.k1 = lead ? base + w1 : 0u;
+    r.bits = bits;
+    r.slot = ((base + w1) * 0x9e3779b1u) >> (32 - P.wlog);
+    r.old = P.wtab[r.slot];
+    return r;
+}
+
+// Keeps the compiler from sinking the probes' slot reads into their commits,
+// so that the reads of one step are in flight together.
+__device__ __forceinline__ void probes_issued() { asm volatile("" ::: "memory"); }
+
+// Second half: the lanes that keep an update merge it into their cache slot.
+// A slot holding another word is taken over and its word goes to HBM.  Every
+// change is a compare-and-swap of the whole entry, so lanes of the wave that
+// meet in one slot serialise correctly.
+__device__ __forceinline__ void word_commit(PassCtx& P, WordProbe r)
+{
+    if (r.k1 == 0) return;
+    unsigned long long old = r.old;
+    for (;;) {
+        const bool mine = (uint32_t)(old >> 32) == r.k1;
+        const unsigned long long want =
+            mine ? (old | r.bits) : (((unsigned long long)r.k1 << 32) | r.bits);
+        if (want == old) break;
+        const unsigned long long prev = atomicCAS(&P.wtab[r.slot], old, want);
+        if (prev == old) {
+            if (!mine && old != 0)
+                atomicOr(&((unsigned*)P.arena)[(uint32_t)(old >> 32) - 1], (uint32_t)old);
+            break;
         }
+        old = prev;
     }
-    return __popcll(__ballot(added));
 }
 
 // One pass (representative block, wave or layer interval) over the segments
@@ -957,7 +982,6 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     const uint32_t off_s = (uint32_t)((PASS == PASS_L ? TS.tag_off : TS.off) >> 2);
     const uint32_t off_l = (uint32_t)(TL.off >> 2);
     const uint32_t words_s = (uint32_t)TS.words, words_l = (uint32_t)TL.words;
-    const int wflush = (1 << (P.wlog - 1)) - 2 * kLanes;  // flush before a step could pass half
 
     for (int e0 = 0; e0 < E; e0 += kLanes) {
         const int n_in = E - e0 < kLanes ? E - e0 : kLanes;
@@ -1053,8 +1077,11 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                             if (__ballot(valid && !ok)) P.err |= 1;
                             bool act = valid && ok;
                             if (DENSE) {
-                                new0 = bitmap_or(P, bs, act, (uint32_t)(us + readlane64(ic.fs, q) - 1));
-                                new1 = bitmap_or(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                                WordProbe a = word_probe(P, bs, act, (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                                WordProbe b = word_probe(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                                probes_issued();
+                                word_commit(P, a);
+                                word_commit(P, b);
                             } else {
                                 uint64_t ks = act ? (uint64_t)(us + readlane64(ic.fs, q)) : 0;
                                 uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
@@ -1068,9 +1095,12 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         if (__ballot(valid && !ok)) P.err |= 1;
                         bool act = valid && ok;
                         if (DENSE) {
-                            new0 = bitmap_or(P, bs + (st ? words_s : 0u), act,
-                                             (uint32_t)(us + readlane64(ic.fs, q) - 1));
-                            new1 = bitmap_or(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                            WordProbe a = word_probe(P, bs + (st ? words_s : 0u), act,
+                                                     (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                            WordProbe b = word_probe(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                            probes_issued();
+                            word_commit(P, a);
+                            word_commit(P, b);
                         } else {
                             uint64_t ks =
                                 act ? (((uint64_t)(us + readlane64(ic.fs, q)) << 2) | (st ? 2u : 1u)) : 0;
@@ -1082,11 +1112,14 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         bool ok = (uint64_t)ul < (uint64_t)span_l;
                         if (__ballot(valid && !ok)) P.err |= 1;
                         if (DENSE) {
-                            new1 = bitmap_or(P, bl, valid && ok, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                            WordProbe b = word_probe(P, bl, valid && ok, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
                             if (do_sec) {
                                 bool in = valid && (uint64_t)us < (uint64_t)span_s;
-                                new0 = bitmap_or(P, bs, in, (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                                WordProbe a = word_probe(P, bs, in, (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                                probes_issued();
+                                word_commit(P, a);
                             }
+                            word_commit(P, b);
                         } else {
                             uint64_t kl = (valid && ok)
                                               ? ((((uint64_t)(ul + readlane64(ic.fl, q))) << line_pb) | tag)
@@ -1101,12 +1134,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         }
                     }
                 }
-                if (DENSE) {
-                    P.wfill += new0 + new1;
-                    if (P.wfill > wflush) flush_words(P);
-                } else {
-                    step_sync<PASS>(P, new0, new1, do_sec);
-                }
+                if (!DENSE) step_sync<PASS>(P, new0, new1, do_sec);
             }
         }
     }
@@ -1191,10 +1219,8 @@ __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work
         P.fill0 = P.fill1 = 0;
         P.step = 0;
         P.err = 0;
-        P.wkey = (uint32_t*)lds + (size_t)wave * lds_slots;
-        P.wbits = P.wkey + lds_slots / 2;
+        P.wtab = lds + (size_t)wave * (lds_slots / 2);
         P.wlog = llog - 1;
-        P.wfill = 0;
         const int dense_bits = __builtin_amdgcn_readfirstlane(c.dense);
         const bool dense = (dense_bits & (pass == PASS_B ? 1 : 2)) != 0;
         if (c.kind == 0) {
