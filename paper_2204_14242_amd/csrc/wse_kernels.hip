@@ -865,8 +865,8 @@ __device__ __forceinline__ void flush_words(PassCtx& P)
     wave_fence();
 }
 
-// One lane's pending update of a bitmap word: the merged bits of its run of
-// equal words, the word's cache slot and the slot's content when read.
+// One lane's pending update of a bitmap word: the merged bits it writes, the
+// word's cache slot and the slot's content when read.
 struct WordProbe {
     unsigned long long old;
     uint32_t k1;      // word offset + 1; 0 = this lane has nothing to write
@@ -874,13 +874,23 @@ struct WordProbe {
     uint32_t slot;
 };
 
+// How far lanes merge their bits before writing: 0 = not at all (only lanes
+// repeating the next lane's key stay silent), 2 = within aligned groups of
+// 4 lanes, 4 = within rows of 16, 6 = across the wave.
+constexpr int kMergeSteps = 6;
+
+__device__ __forceinline__ uint32_t dpp_merge(uint32_t bits, uint32_t w1, uint32_t src_bits, uint32_t src_w1)
+{
+    return bits | (src_bits & (0u - (uint32_t)(src_w1 == w1)));
+}
+
 // First half of setting bit `key` of the bitmap at word offset `base` for
-// every lane with `act`: lanes merge the bits of equal words across the
-// wave (an OR-scan over lanes whose word matches: DPP row shifts 1, 2, 4, 8
-// within rows of 16 lanes, then the last lane of rows 0 and 2 into rows 1
-// and 3, and lane 31 into rows 2 and 3), the last lane of each run of equal
-// words keeps the update, and every lane reads its cache slot.  Must be
-// called by all lanes of the wave.
+// every lane with `act`: lanes merge the bits of equal words (an OR-scan over
+// lanes whose word matches: DPP row shifts 1, 2, 4, 8 within rows of 16
+// lanes, then the last lane of rows 0 and 2 into rows 1 and 3, and lane 31
+// into rows 2 and 3, as far as kMergeSteps goes), the lanes whose merged
+// bits nobody after them covers keep the update, and every lane reads its
+// cache slot.  Must be called by all lanes of the wave.
 __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base, bool act, uint32_t key)
 {
     // word index + 1 (< 2^27); lanes without a key hold a value no word
@@ -888,24 +898,36 @@ __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base,
     // mask read 0
     const uint32_t w1 = act ? (key >> 5) + 1 : 0xffffffffu;
     uint32_t bits = act ? 1u << (key & 31) : 0u;
-    bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x111, 0xf, 0xf, true) &
-            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x111, 0xf, 0xf, true) == w1));
-    bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x112, 0xf, 0xf, true) &
-            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x112, 0xf, 0xf, true) == w1));
-    bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x114, 0xf, 0xf, true) &
-            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x114, 0xf, 0xf, true) == w1));
-    bits |= (uint32_t)__builtin_amdgcn_mov_dpp((int)bits, 0x118, 0xf, 0xf, true) &
-            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x118, 0xf, 0xf, true) == w1));
-    // row_bcast:15 into rows 1 and 3, then row_bcast:31 into rows 2 and 3
-    // (other rows keep the 0 of `old`)
-    bits |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x142, 0xa, 0xf, false) &
-            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_update_dpp(0, (int)w1, 0x142, 0xa, 0xf, false) == w1));
-    bits |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)bits, 0x143, 0xc, 0xf, false) &
-            (0u - (uint32_t)((uint32_t)__builtin_amdgcn_update_dpp(0, (int)w1, 0x143, 0xc, 0xf, false) == w1));
-    // wave_shl:1: the next lane's word (0 past lane 63)
-    const uint32_t nw1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x130, 0xf, 0xf, true);
+    bool lead;
+    if (kMergeSteps == 0) {
+        const uint32_t k1 = act ? key + 1 : 0u;
+        lead = act && (uint32_t)__builtin_amdgcn_mov_dpp((int)k1, 0x130, 0xf, 0xf, true) != k1;
+    } else {
+        bits = dpp_merge(bits, w1, __builtin_amdgcn_mov_dpp((int)bits, 0x111, 0xf, 0xf, true),
+                         __builtin_amdgcn_mov_dpp((int)w1, 0x111, 0xf, 0xf, true));
+        bits = dpp_merge(bits, w1, __builtin_amdgcn_mov_dpp((int)bits, 0x112, 0xf, 0xf, true),
+                         __builtin_amdgcn_mov_dpp((int)w1, 0x112, 0xf, 0xf, true));
+        if (kMergeSteps >= 4) {
+            bits = dpp_merge(bits, w1, __builtin_amdgcn_mov_dpp((int)bits, 0x114, 0xf, 0xf, true),
+                             __builtin_amdgcn_mov_dpp((int)w1, 0x114, 0xf, 0xf, true));
+            bits = dpp_merge(bits, w1, __builtin_amdgcn_mov_dpp((int)bits, 0x118, 0xf, 0xf, true),
+                             __builtin_amdgcn_mov_dpp((int)w1, 0x118, 0xf, 0xf, true));
+        }
+        if (kMergeSteps >= 6) {
+            // row_bcast:15 into rows 1 and 3, then row_bcast:31 into rows 2
+            // and 3 (other rows keep the 0 of `old`)
+            bits = dpp_merge(bits, w1, __builtin_amdgcn_update_dpp(0, (int)bits, 0x142, 0xa, 0xf, false),
+                             __builtin_amdgcn_update_dpp(0, (int)w1, 0x142, 0xa, 0xf, false));
+            bits = dpp_merge(bits, w1, __builtin_amdgcn_update_dpp(0, (int)bits, 0x143, 0xc, 0xf, false),
+                             __builtin_amdgcn_update_dpp(0, (int)w1, 0x143, 0xc, 0xf, false));
+        }
+        // the last lane of a run of equal words writes, and so does the last
+        // lane of every group the scan stays inside
+        const uint32_t nw1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x130, 0xf, 0xf, true);
+        const int group = kMergeSteps >= 6 ? 64 : (kMergeSteps >= 4 ? 16 : 4);
+        lead = act && (nw1 != w1 || (lane_id() & (group - 1)) == group - 1);
+    }
     WordProbe r;
-    const bool lead = act && nw1 != w1;
     r.k1 = lead ? base + w1 : 0u;
     r.bits = bits;
     r.slot = ((base + w1) * 0x9e3779b1u) >> (32 - P.wlog);
@@ -917,26 +939,44 @@ __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base,
 // so that the reads of one step are in flight together.
 __device__ __forceinline__ void probes_issued() { asm volatile("" ::: "memory"); }
 
-// Second half: the lanes that keep an update merge it into their cache slot.
-// A slot holding another word is taken over and its word goes to HBM.  Every
-// change is a compare-and-swap of the whole entry, so lanes of the wave that
-// meet in one slot serialise correctly.
-__device__ __forceinline__ void word_commit(PassCtx& P, WordProbe r)
+// Second half, first part: lanes whose slot already holds their word OR
+// their bits into it (tags do not change here, so every probe of the step
+// is still valid).  Clears k1 of the lanes it served.
+__device__ __forceinline__ void word_commit_or(PassCtx& P, WordProbe& r)
+{
+    if (r.k1 != 0 && (uint32_t)(r.old >> 32) == r.k1) {
+        if ((r.old | r.bits) != r.old) atomicOr(&P.wtab[r.slot], (unsigned long long)r.bits);
+        r.k1 = 0;
+    }
+}
+
+// Second part: lanes whose slot held another word (or none) take the slot
+// over by compare-and-swap of the whole entry, sending the displaced word to
+// HBM; a lane that finds its word installed meanwhile ORs into it.  Within
+// one pass of the loop the ORs precede the swaps, so no OR can land in a
+// slot that a swap of the same pass has just handed to another word.
+__device__ __forceinline__ void word_commit_cas(PassCtx& P, WordProbe r)
 {
     if (r.k1 == 0) return;
     unsigned long long old = r.old;
-    for (;;) {
+    bool done = false;
+    while (!done) {
         const bool mine = (uint32_t)(old >> 32) == r.k1;
-        const unsigned long long want =
-            mine ? (old | r.bits) : (((unsigned long long)r.k1 << 32) | r.bits);
-        if (want == old) break;
-        const unsigned long long prev = atomicCAS(&P.wtab[r.slot], old, want);
-        if (prev == old) {
-            if (!mine && old != 0)
-                atomicOr(&((unsigned*)P.arena)[(uint32_t)(old >> 32) - 1], (uint32_t)old);
-            break;
+        if (mine) {
+            if ((old | r.bits) != old) atomicOr(&P.wtab[r.slot], (unsigned long long)r.bits);
+            done = true;
         }
-        old = prev;
+        asm volatile("" ::: "memory");  // the ORs stay ahead of the swaps
+        if (!mine) {
+            const unsigned long long want = ((unsigned long long)r.k1 << 32) | r.bits;
+            const unsigned long long prev = atomicCAS(&P.wtab[r.slot], old, want);
+            if (prev == old) {
+                if (old != 0) atomicOr(&((unsigned*)P.arena)[(uint32_t)(old >> 32) - 1], (uint32_t)old);
+                done = true;
+            } else {
+                old = prev;
+            }
+        }
     }
 }
 
@@ -1080,8 +1120,10 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                                 WordProbe a = word_probe(P, bs, act, (uint32_t)(us + readlane64(ic.fs, q) - 1));
                                 WordProbe b = word_probe(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
                                 probes_issued();
-                                word_commit(P, a);
-                                word_commit(P, b);
+                                word_commit_or(P, a);
+                                word_commit_or(P, b);
+                                word_commit_cas(P, a);
+                                word_commit_cas(P, b);
                             } else {
                                 uint64_t ks = act ? (uint64_t)(us + readlane64(ic.fs, q)) : 0;
                                 uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
@@ -1099,8 +1141,10 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                                                      (uint32_t)(us + readlane64(ic.fs, q) - 1));
                             WordProbe b = word_probe(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
                             probes_issued();
-                            word_commit(P, a);
-                            word_commit(P, b);
+                            word_commit_or(P, a);
+                            word_commit_or(P, b);
+                            word_commit_cas(P, a);
+                            word_commit_cas(P, b);
                         } else {
                             uint64_t ks =
                                 act ? (((uint64_t)(us + readlane64(ic.fs, q)) << 2) | (st ? 2u : 1u)) : 0;
@@ -1113,13 +1157,16 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         if (__ballot(valid && !ok)) P.err |= 1;
                         if (DENSE) {
                             WordProbe b = word_probe(P, bl, valid && ok, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                            WordProbe a = {0ull, 0u, 0u, 0u};
                             if (do_sec) {
                                 bool in = valid && (uint64_t)us < (uint64_t)span_s;
-                                WordProbe a = word_probe(P, bs, in, (uint32_t)(us + readlane64(ic.fs, q) - 1));
-                                probes_issued();
-                                word_commit(P, a);
+                                a = word_probe(P, bs, in, (uint32_t)(us + readlane64(ic.fs, q) - 1));
                             }
-                            word_commit(P, b);
+                            probes_issued();
+                            word_commit_or(P, b);
+                            word_commit_or(P, a);
+                            word_commit_cas(P, b);
+                            word_commit_cas(P, a);
                         } else {
                             uint64_t kl = (valid && ok)
                                               ? ((((uint64_t)(ul + readlane64(ic.fl, q))) << line_pb) | tag)
