@@ -713,9 +713,9 @@ struct PassCtx {
     int fill0, fill1;          // running fills of the sets, the same in every wave
     int step;
     uint64_t err;
-    // bitmap configurations: this wave's direct-mapped LDS cache of bitmap
-    // words, entries ((offset + 1) << 32) | bits for the word at `offset` in
-    // the configuration's tables; 0 = empty
+    // bitmap configurations: the workgroup's direct-mapped LDS cache of
+    // bitmap words, entries ((offset + 1) << 32) | bits for the word at
+    // `offset` in the configuration's tables; 0 = empty
     unsigned long long* wtab;
     int wlog;                  // 2^wlog entries
 };
@@ -850,19 +850,19 @@ __device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, const Tab
 
 __device__ __forceinline__ int32_t readlane32(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
-// Move this wave's cache of bitmap words into the configuration's bitmaps in
-// HBM (one atomic OR per word) and clear it.
+// Move the workgroup's cache of bitmap words into the configuration's
+// bitmaps in HBM (one atomic OR per word) and clear it; all threads of the
+// workgroup take part.
 __device__ __forceinline__ void flush_words(PassCtx& P)
 {
     unsigned* words = (unsigned*)P.arena;
     const int n = 1 << P.wlog;
-    for (int i = lane_id(); i < n; i += kLanes) {
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
         const unsigned long long e = P.wtab[i];
         if (e == 0) continue;
         P.wtab[i] = 0;
         atomicOr(&words[(uint32_t)(e >> 32) - 1], (uint32_t)e);
     }
-    wave_fence();
 }
 
 // One lane's pending update of a bitmap word: the merged bits it writes, the
@@ -939,44 +939,26 @@ __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base,
 // so that the reads of one step are in flight together.
 __device__ __forceinline__ void probes_issued() { asm volatile("" ::: "memory"); }
 
-// Second half, first part: lanes whose slot already holds their word OR
-// their bits into it (tags do not change here, so every probe of the step
-// is still valid).  Clears k1 of the lanes it served.
-__device__ __forceinline__ void word_commit_or(PassCtx& P, WordProbe& r)
-{
-    if (r.k1 != 0 && (uint32_t)(r.old >> 32) == r.k1) {
-        if ((r.old | r.bits) != r.old) atomicOr(&P.wtab[r.slot], (unsigned long long)r.bits);
-        r.k1 = 0;
-    }
-}
-
-// Second part: lanes whose slot held another word (or none) take the slot
-// over by compare-and-swap of the whole entry, sending the displaced word to
-// HBM; a lane that finds its word installed meanwhile ORs into it.  Within
-// one pass of the loop the ORs precede the swaps, so no OR can land in a
-// slot that a swap of the same pass has just handed to another word.
-__device__ __forceinline__ void word_commit_cas(PassCtx& P, WordProbe r)
+// Second half: the lanes that keep an update merge it into their cache slot.
+// A slot holding another word is taken over and its word goes to HBM.  Every
+// change is a compare-and-swap of the whole entry, so lanes and waves that
+// meet in one slot serialise correctly.
+__device__ __forceinline__ void word_commit(PassCtx& P, WordProbe r)
 {
     if (r.k1 == 0) return;
     unsigned long long old = r.old;
-    bool done = false;
-    while (!done) {
+    for (;;) {
         const bool mine = (uint32_t)(old >> 32) == r.k1;
-        if (mine) {
-            if ((old | r.bits) != old) atomicOr(&P.wtab[r.slot], (unsigned long long)r.bits);
-            done = true;
+        const unsigned long long want =
+            mine ? (old | r.bits) : (((unsigned long long)r.k1 << 32) | r.bits);
+        if (want == old) break;
+        const unsigned long long prev = atomicCAS(&P.wtab[r.slot], old, want);
+        if (prev == old) {
+            if (!mine && old != 0)
+                atomicOr(&((unsigned*)P.arena)[(uint32_t)(old >> 32) - 1], (uint32_t)old);
+            break;
         }
-        asm volatile("" ::: "memory");  // the ORs stay ahead of the swaps
-        if (!mine) {
-            const unsigned long long want = ((unsigned long long)r.k1 << 32) | r.bits;
-            const unsigned long long prev = atomicCAS(&P.wtab[r.slot], old, want);
-            if (prev == old) {
-                if (old != 0) atomicOr(&((unsigned*)P.arena)[(uint32_t)(old >> 32) - 1], (uint32_t)old);
-                done = true;
-            } else {
-                old = prev;
-            }
-        }
+        old = prev;
     }
 }
 
@@ -1030,19 +1012,15 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
         else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}};
         const int32_t meta = ic.st | (ic.elem << 1);
 
-        // hash configurations: the waves interleave segments in lockstep;
-        // bitmap configurations: each wave takes a contiguous quarter
-        const int64_t quarter = (j1 - j0 + kWavesPerGroup - 1) / kWavesPerGroup;
-        const int64_t ja = DENSE ? (j0 + P.wave * quarter < j1 ? j0 + P.wave * quarter : j1) : j0;
-        const int64_t jb = DENSE ? (ja + quarter < j1 ? ja + quarter : j1) : j1;
-        const int jstep = DENSE ? 1 : kWavesPerGroup;
+        // the waves interleave segments (hash configurations in lockstep)
         // this wave's first segment: block k, segment sgi, block coordinates
-        int64_t jw = DENSE ? ja : j0 + P.wave;
+        int64_t jw = j0 + P.wave;
         int64_t k = k_lo + jw / spb;
         int sgi = (int)(jw % spb);
         int64_t bx = k % nb0, by = (k / nb0) % nb1, bz = k / (nb0 * nb1);
-        for (int64_t jg = ja; jg < jb; jg += jstep) {
-            const bool seg_ok = DENSE || jg + P.wave < j1;
+        for (int64_t jg = j0; jg < j1; jg += kWavesPerGroup) {
+            const bool seg_ok = jg + P.wave < j1;
+            if (DENSE && !seg_ok) break;
             const int64_t t = (int64_t)sgi * kLanes + lane;
             const bool inb = t < Pthr;
             const int64_t tx = t & (b0 - 1), ty = (t >> lb0) & (b1 - 1), tz = t >> (lb0 + lb1);
@@ -1053,7 +1031,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             const int64_t bcur[3] = {bx, by, bz};
             const int64_t tcur[3] = {tx, ty, tz};
             // advance to the wave's next segment
-            for (int step = 0; step < jstep; step++) {
+            for (int step = 0; step < kWavesPerGroup; step++) {
                 if (++sgi == spb) {
                     sgi = 0;
                     k++;
@@ -1120,10 +1098,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                                 WordProbe a = word_probe(P, bs, act, (uint32_t)(us + readlane64(ic.fs, q) - 1));
                                 WordProbe b = word_probe(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
                                 probes_issued();
-                                word_commit_or(P, a);
-                                word_commit_or(P, b);
-                                word_commit_cas(P, a);
-                                word_commit_cas(P, b);
+                                word_commit(P, a);
+                                word_commit(P, b);
                             } else {
                                 uint64_t ks = act ? (uint64_t)(us + readlane64(ic.fs, q)) : 0;
                                 uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
@@ -1141,10 +1117,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                                                      (uint32_t)(us + readlane64(ic.fs, q) - 1));
                             WordProbe b = word_probe(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
                             probes_issued();
-                            word_commit_or(P, a);
-                            word_commit_or(P, b);
-                            word_commit_cas(P, a);
-                            word_commit_cas(P, b);
+                            word_commit(P, a);
+                            word_commit(P, b);
                         } else {
                             uint64_t ks =
                                 act ? (((uint64_t)(us + readlane64(ic.fs, q)) << 2) | (st ? 2u : 1u)) : 0;
@@ -1163,10 +1137,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                                 a = word_probe(P, bs, in, (uint32_t)(us + readlane64(ic.fs, q) - 1));
                             }
                             probes_issued();
-                            word_commit_or(P, b);
-                            word_commit_or(P, a);
-                            word_commit_cas(P, b);
-                            word_commit_cas(P, a);
+                            word_commit(P, b);
+                            word_commit(P, a);
                         } else {
                             uint64_t kl = (valid && ok)
                                               ? ((((uint64_t)(ul + readlane64(ic.fl, q))) << line_pb) | tag)
@@ -1186,8 +1158,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
         }
     }
     if (DENSE) {
-        // final flush of the wave's words; then no wave may start on the next
-        // item (whose LDS use may differ) before all have flushed
+        // final flush of the workgroup's cached words
+        __syncthreads();
         flush_words(P);
         __syncthreads();
     } else {
@@ -1266,8 +1238,8 @@ __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work
         P.fill0 = P.fill1 = 0;
         P.step = 0;
         P.err = 0;
-        P.wtab = lds + (size_t)wave * (lds_slots / 2);
-        P.wlog = llog - 1;
+        P.wtab = lds;
+        P.wlog = llog + 1;
         const int dense_bits = __builtin_amdgcn_readfirstlane(c.dense);
         const bool dense = (dense_bits & (pass == PASS_B ? 1 : 2)) != 0;
         if (c.kind == 0) {
