@@ -879,7 +879,7 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
         };
         add(0, PASS_B, spb, per);
         add(0, PASS_W, (g.w1 - g.w0) * spb, per);
-        if (g.smin >= 0) add(1, PASS_L, (g.w0 - g.smin) * spb, per);
+        if (g.smin >= 0) add(1, PASS_L, g.l_units, per);
         for (int t = 0; t < N_TABLES; t++)
             if (table_used(g.tab[t])) add(2, t, table_units(g.tab[t]), 1 << 16);
     }

@@ -112,6 +112,7 @@ struct Cfg {
     int32_t pad2;
     int64_t sy, sz, g;
     int64_t evals[3];           // thread x instruction evaluations per pass (upper bound)
+    int64_t l_units;            // layer pass: segments of its blocks' threads in row order
     TableDesc tab[N_TABLES];
     int64_t table_bytes;        // arena bytes this configuration needs
 };

@@ -250,6 +250,77 @@ hipError_t launch_expand(const ExpandJob* jobs_dev, int n_jobs, DevTables t, hip
 
 // ---------------------------------------------------------------- decode
 
+// Row order of a block interval [klo, khi): the threads of its blocks taken
+// as runs of consecutive x along the rows of the thread grid.  The interval
+// covers whole rows of blocks (fixed by, bz) except possibly a first and a
+// last partial one; each row of blocks holds b1 * b2 thread rows, and each
+// thread row an x range cut into segments of 64.  Units are ordered by row
+// of blocks, then thread row (ty fastest), then segment.
+struct RowOrder {
+    int64_t r0, rl;           // first and last row of blocks
+    int64_t xa0, xb0, xal, xbl;  // x ranges (threads) of the first and last row
+    int64_t nseg0, nsegm, nsegl;  // segments per thread row: first, middle, last rows
+    int64_t s0, sm, nmid;     // units of the first row, of each middle row; middle rows
+    int64_t units;
+};
+
+__device__ __forceinline__ RowOrder row_order(const Cfg& c, int64_t klo, int64_t khi)
+{
+    RowOrder o;
+    const int64_t nb0 = c.nb[0], b0 = c.b[0], T0 = c.T[0];
+    const int64_t rows = (int64_t)c.b[1] * c.b[2];
+    o.r0 = klo / nb0;
+    o.rl = (khi - 1) / nb0;
+    const int64_t bxa = klo % nb0, bxb = (khi - 1) % nb0;
+    o.xa0 = bxa * b0;
+    o.xb0 = o.r0 == o.rl ? (bxb + 1) * b0 : nb0 * b0;
+    o.xal = 0;
+    o.xbl = (bxb + 1) * b0;
+    if (o.xb0 > T0) o.xb0 = T0;
+    if (o.xbl > T0) o.xbl = T0;
+    o.nseg0 = (o.xb0 - o.xa0 + kLanes - 1) / kLanes;
+    o.nsegm = (T0 + kLanes - 1) / kLanes;
+    o.nsegl = o.r0 == o.rl ? 0 : (o.xbl - o.xal + kLanes - 1) / kLanes;
+    o.s0 = rows * o.nseg0;
+    o.sm = rows * o.nsegm;
+    o.nmid = o.rl - o.r0 - 1 > 0 ? o.rl - o.r0 - 1 : 0;
+    o.units = o.s0 + o.nmid * o.sm + rows * o.nsegl;
+    return o;
+}
+
+// unit j of a row order: row of blocks r, thread row (ty, tz), first x of
+// the segment and end of the row's x range
+__device__ __forceinline__ void row_unit(const RowOrder& o, const Cfg& c, int64_t j, int64_t* r, int64_t* ty,
+                                         int64_t* tz, int64_t* x0, int64_t* xe)
+{
+    int64_t loc, nseg, xa;
+    if (j < o.s0) {
+        *r = o.r0;
+        loc = j;
+        nseg = o.nseg0;
+        xa = o.xa0;
+        *xe = o.xb0;
+    } else if (j - o.s0 < o.nmid * o.sm) {
+        const int64_t jm = j - o.s0;
+        *r = o.r0 + 1 + jm / o.sm;
+        loc = jm % o.sm;
+        nseg = o.nsegm;
+        xa = 0;
+        *xe = c.T[0];
+    } else {
+        *r = o.rl;
+        loc = j - o.s0 - o.nmid * o.sm;
+        nseg = o.nsegl;
+        xa = o.xal;
+        *xe = o.xbl;
+    }
+    const int64_t tr = loc / nseg;
+    *x0 = xa + (loc % nseg) * kLanes;
+    *ty = tr & (c.b[1] - 1);
+    *tz = tr >> c.lb[1];
+}
+
+
 struct Range {
     int64_t lo, hi;
 };
@@ -472,6 +543,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
     c.evals[PASS_B] = c.P * c.E;
     c.evals[PASS_W] = (c.w1 - c.w0) * c.P * c.E;
     c.evals[PASS_L] = nL * c.P * c.E;
+    c.l_units = nL > 0 ? row_order(c, c.smin, c.w0).units : 0;
     c.tag_bits = bits_for((uint64_t)(nL + 1));
     const Expansion* X = S.kind == 0 ? &t.expansions[c.expansion_id] : nullptr;
     int bad = 0;
@@ -874,9 +946,8 @@ struct WordProbe {
     uint32_t slot;
 };
 
-// How far lanes merge their bits before writing: 0 = not at all (only lanes
-// repeating the next lane's key stay silent), 2 = within aligned groups of
-// 4 lanes, 4 = within rows of 16, 6 = across the wave.
+// How far lanes merge their bits before writing: 2 = within aligned groups
+// of 4 lanes, 4 = within rows of 16, 6 = across the wave.
 constexpr int kMergeSteps = 6;
 
 __device__ __forceinline__ uint32_t dpp_merge(uint32_t bits, uint32_t w1, uint32_t src_bits, uint32_t src_w1)
@@ -884,8 +955,8 @@ __device__ __forceinline__ uint32_t dpp_merge(uint32_t bits, uint32_t w1, uint32
     return bits | (src_bits & (0u - (uint32_t)(src_w1 == w1)));
 }
 
-// First half of setting bit `key` of the bitmap at word offset `base` for
-// every lane with `act`: lanes merge the bits of equal words (an OR-scan over
+// First half of setting bit `key` of the bitmap at word offset `base` (per
+// lane) for every lane with `act`: lanes merge the bits of equal words (an OR-scan over
 // lanes whose word matches: DPP row shifts 1, 2, 4, 8 within rows of 16
 // lanes, then the last lane of rows 0 and 2 into rows 1 and 3, and lane 31
 // into rows 2 and 3, as far as kMergeSteps goes), the lanes whose merged
@@ -893,16 +964,14 @@ __device__ __forceinline__ uint32_t dpp_merge(uint32_t bits, uint32_t w1, uint32
 // cache slot.  Must be called by all lanes of the wave.
 __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base, bool act, uint32_t key)
 {
-    // word index + 1 (< 2^27); lanes without a key hold a value no word
-    // has, and lanes whose DPP source lies outside the wave, row or row
-    // mask read 0
-    const uint32_t w1 = act ? (key >> 5) + 1 : 0xffffffffu;
+    // word offset + 1 in the configuration's tables (< 2^31; `base` may
+    // differ between lanes); lanes without a key hold a value no word has,
+    // and lanes whose DPP source lies outside the wave, row or row mask
+    // read 0
+    const uint32_t w1 = act ? base + (key >> 5) + 1 : 0xffffffffu;
     uint32_t bits = act ? 1u << (key & 31) : 0u;
     bool lead;
-    if (kMergeSteps == 0) {
-        const uint32_t k1 = act ? key + 1 : 0u;
-        lead = act && (uint32_t)__builtin_amdgcn_mov_dpp((int)k1, 0x130, 0xf, 0xf, true) != k1;
-    } else {
+    {
         bits = dpp_merge(bits, w1, __builtin_amdgcn_mov_dpp((int)bits, 0x111, 0xf, 0xf, true),
                          __builtin_amdgcn_mov_dpp((int)w1, 0x111, 0xf, 0xf, true));
         bits = dpp_merge(bits, w1, __builtin_amdgcn_mov_dpp((int)bits, 0x112, 0xf, 0xf, true),
@@ -928,9 +997,9 @@ __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base,
         lead = act && (nw1 != w1 || (lane_id() & (group - 1)) == group - 1);
     }
     WordProbe r;
-    r.k1 = lead ? base + w1 : 0u;
+    r.k1 = lead ? w1 : 0u;
     r.bits = bits;
-    r.slot = ((base + w1) * 0x9e3779b1u) >> (32 - P.wlog);
+    r.slot = (w1 * 0x9e3779b1u) >> (32 - P.wlog);
     r.old = P.wtab[r.slot];
     return r;
 }
@@ -1004,6 +1073,10 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     const uint32_t off_s = (uint32_t)((PASS == PASS_L ? TS.tag_off : TS.off) >> 2);
     const uint32_t off_l = (uint32_t)(TL.off >> 2);
     const uint32_t words_s = (uint32_t)TS.words, words_l = (uint32_t)TL.words;
+    // layer pass: row order of its blocks; band thresholds in recency order
+    RowOrder ro;
+    if (PASS == PASS_L) ro = row_order(c, c.smin, c.w0);
+    const int64_t s_band[2] = {c.n_order > 0 ? c.s[c.order[0]] : 0, c.n_order > 1 ? c.s[c.order[1]] : 0};
 
     for (int e0 = 0; e0 < E; e0 += kLanes) {
         const int n_in = E - e0 < kLanes ? E - e0 : kLanes;
@@ -1021,14 +1094,37 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
         for (int64_t jg = j0; jg < j1; jg += kWavesPerGroup) {
             const bool seg_ok = jg + P.wave < j1;
             if (DENSE && !seg_ok) break;
-            const int64_t t = (int64_t)sgi * kLanes + lane;
-            const bool inb = t < Pthr;
-            const int64_t tx = t & (b0 - 1), ty = (t >> lb0) & (b1 - 1), tz = t >> (lb0 + lb1);
-            const int64_t gx = bx * b0 + tx, gy = by * b1 + ty, gz = bz * b2 + tz;
-            const bool valid = seg_ok && inb && gx < T0 && gy < T1 && gz < T2;
+            int64_t tx, ty, tz, gx, gy, gz, kcur, bcur[3];
+            bool valid;
+            if (PASS == PASS_L) {
+                // row order: 64 consecutive x of one thread row
+                int64_t r, x0, xe;
+                row_unit(ro, c, seg_ok ? jg + P.wave : 0, &r, &ty, &tz, &x0, &xe);
+                bcur[1] = r % nb1;
+                bcur[2] = r / nb1;
+                gx = x0 + lane;
+                gy = bcur[1] * b1 + ty;
+                gz = bcur[2] * b2 + tz;
+                bcur[0] = gx >> lb0;
+                tx = gx & (b0 - 1);
+                kcur = bcur[0] + nb0 * r;
+                valid = seg_ok && gx < xe && gy < T1 && gz < T2;
+            } else {
+                const int64_t t = (int64_t)sgi * kLanes + lane;
+                const bool inb = t < Pthr;
+                tx = t & (b0 - 1);
+                ty = (t >> lb0) & (b1 - 1);
+                tz = t >> (lb0 + lb1);
+                gx = bx * b0 + tx;
+                gy = by * b1 + ty;
+                gz = bz * b2 + tz;
+                valid = seg_ok && inb && gx < T0 && gy < T1 && gz < T2;
+                kcur = k;
+                bcur[0] = bx;
+                bcur[1] = by;
+                bcur[2] = bz;
+            }
             const uint64_t vmask = __ballot(valid);
-            const int64_t kcur = k;
-            const int64_t bcur[3] = {bx, by, bz};
             const int64_t tcur[3] = {tx, ty, tz};
             // advance to the wave's next segment
             for (int step = 0; step < kWavesPerGroup; step++) {
@@ -1055,14 +1151,16 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 }
             }
             if (DENSE && vmask == 0) continue;
+            // layer pass: each lane's block tag, or its layer band (bitmaps):
+            // the first set, in recency order, whose start the block reaches
             const uint64_t tag = PASS == PASS_L ? (uint64_t)(kcur - smin + 1) : 0;
-            // layer band of this segment's block (bitmaps): the first set, in
-            // recency order, whose start the block reaches
-            int band = 0;
-            if (DENSE && PASS == PASS_L)
-                while (band < c.n_order - 1 && kcur < c.s[c.order[band]]) band++;
-            const uint32_t bl = off_l + (PASS == PASS_L ? (uint32_t)band * words_l : 0u);
-            const uint32_t bs = off_s + (PASS == PASS_L ? (uint32_t)band * words_s : 0u);
+            uint32_t band = 0;
+            if (DENSE && PASS == PASS_L) {
+                if (c.n_order > 1 && kcur < s_band[0]) band = 1;
+                if (c.n_order > 2 && kcur < s_band[1]) band = 2;
+            }
+            const uint32_t bl = off_l + band * words_l;
+            const uint32_t bs = off_s + band * words_s;
             int64_t base = 0;
             if (KIND == 0) base = (gx + g) + sy * (f1 * gy + g) + sz * (f2 * gz + g);
             const int64_t ubase = uelem ? base * uelem : 0;
