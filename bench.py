@@ -187,6 +187,8 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     st = ctx.last_stats()
+    # per-configuration evaluation counts of the workload, for the CPU baseline
+    per_config_evals = ctx.last_evals(n).astype(np.float64)
     evals = st["evals"] * a.steps
     launches = st["eval_launches"] * a.steps
     res = np.frombuffer(out.cpu().numpy().tobytes(), dtype=wsest.RESULT_DTYPE)
@@ -218,9 +220,7 @@ def main():
     if a.serve_requests > 0:
         line["served"] = served(ctx, a.serve_requests)
     if not a.no_cpu_baseline:
-        # per-configuration evaluation counts of the workload, from the last GPU step
-        per = ctx.last_evals(n).astype(np.float64)
-        line["cpu_baseline"] = cpu_baseline(kernel, hw, space, per, a.cpu_budget_s)
+        line["cpu_baseline"] = cpu_baseline(kernel, hw, space, per_config_evals, a.cpu_budget_s)
     print(json.dumps(line), flush=True)
     ctx.close()
 
