@@ -211,6 +211,8 @@ struct wse_ctx {
     DevBuf<WorkEntry> d_work;
     DevBuf<RoundDesc> d_rd;
     hipStream_t rs = nullptr;  // stream of the round launches
+    hipStream_t rs2 = nullptr;  // second branch of a round: layer passes of lattice kernels on bitmaps
+    hipEvent_t fork = nullptr, join = nullptr;  // between the two branches
     // captured round graphs: [0] clear + evaluation launches, [1] counting
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -295,10 +297,17 @@ wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out)
     const char* pg = std::getenv("WSE_PROGRESS");
     c->progress = pg && pg[0] == '1';
     e = hipStreamCreateWithFlags(&c->rs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->rs2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
     if (e != hipSuccess) {
+        if (c->join) (void)hipEventDestroy(c->join);
+        if (c->fork) (void)hipEventDestroy(c->fork);
+        if (c->rs2) (void)hipStreamDestroy(c->rs2);
+        if (c->rs) (void)hipStreamDestroy(c->rs);
         (void)hipFree(c->arena);
         delete c;
-        return fail(WSE_EDEVICE, std::string("round stream: ") + hipGetErrorString(e));
+        return fail(WSE_EDEVICE, std::string("round streams: ") + hipGetErrorString(e));
     }
     *out = c;
     return WSE_OK;
@@ -331,6 +340,9 @@ void wse_ctx_destroy(wse_ctx* c)
         if (c->graph_exec[g]) (void)hipGraphExecDestroy(c->graph_exec[g]);
         if (c->graph[g]) (void)hipGraphDestroy(c->graph[g]);
     }
+    if (c->join) (void)hipEventDestroy(c->join);
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->rs2) (void)hipStreamDestroy(c->rs2);
     if (c->rs) (void)hipStreamDestroy(c->rs);
     (void)hipFree(c->arena);
     delete c;
@@ -808,6 +820,25 @@ static void form_round(wse_ctx* c, const std::vector<Job*>& jobs, std::vector<Ro
     }
 }
 
+// The evaluation launches of a round as two branches that fork after the
+// clearing launch queued on the round stream and join back into it: the
+// general launches on the round stream, the lattice bitmap launch on the
+// second stream.  The lattice bitmap layer passes read nothing the general
+// launches write, and the block passes (few, long work items) leave most of
+// the device to them.
+static hipError_t launch_branches(wse_ctx* c, DevTables t, int64_t groups, const int32_t* counts = nullptr)
+{
+    hipError_t e = hipEventRecord(c->fork, c->rs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->rs2, c->fork, 0);
+    if (e == hipSuccess && (!counts || counts[LIST_EVAL_DL]))
+        e = launch_eval(c->d_work.p, c->d_rd.p, LIST_EVAL_DL, t, c->lds_slots, groups, c->rs2);
+    if (e == hipSuccess) e = hipEventRecord(c->join, c->rs2);
+    for (int w = LIST_EVAL_A; w <= LIST_EVAL_B && e == hipSuccess; w++)
+        if (!counts || counts[w]) e = launch_eval(c->d_work.p, c->d_rd.p, w, t, c->lds_slots, groups, c->rs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->rs, c->join, 0);
+    return e;
+}
+
 // (Re)capture the round graphs when anything their kernel arguments name
 // has changed: the work list buffer, the resident tables, the tuning.
 static wse_status ensure_round_graphs(wse_ctx* c, int64_t groups)
@@ -823,11 +854,12 @@ static wse_status ensure_round_graphs(wse_ctx* c, int64_t groups)
         c->graph_exec[g] = nullptr;
         c->graph[g] = nullptr;
     }
-    // graph 0: clear the round's tables, evaluate block+wave, evaluate layers
+    // graph 0: clear the round's tables, then two branches: the general
+    // evaluation launches (block and wave passes, then the layer passes on
+    // hash tables) and, beside them, the lattice bitmap launch
     HIP_TRY(hipStreamBeginCapture(c->rs, hipStreamCaptureModeThreadLocal));
     hipError_t e = launch_round_fill(c->arena, c->d_rd.p, groups, c->rs);
-    if (e == hipSuccess) e = launch_eval(c->d_work.p, c->d_rd.p, 0, t, c->lds_slots, groups, c->rs);
-    if (e == hipSuccess) e = launch_eval(c->d_work.p, c->d_rd.p, 1, t, c->lds_slots, groups, c->rs);
+    if (e == hipSuccess) e = launch_branches(c, t, groups);
     hipError_t e2 = hipStreamEndCapture(c->rs, &c->graph[0]);
     if (e != hipSuccess || e2 != hipSuccess)
         return fail(WSE_EDEVICE, std::string("round graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
@@ -851,9 +883,9 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
                             float* eval_ms, float* count_ms)
 {
     std::vector<WorkEntry> all;
-    int64_t items[3] = {0, 0, 0}, used = 0;
-    int32_t counts[3] = {0, 0, 0};
-    std::vector<WorkEntry> lists[3];
+    int64_t items[N_LISTS] = {0, 0, 0, 0}, used = 0;
+    int32_t counts[N_LISTS] = {0, 0, 0, 0};
+    std::vector<WorkEntry> lists[N_LISTS];
     for (const RoundItem& r : round) {
         const Cfg& g = r.job->cfgs[r.id];
         int64_t base = used;
@@ -877,16 +909,21 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
             items[which] += (units + per_item - 1) / per_item;
             lists[which].push_back(e);
         };
-        add(0, PASS_B, spb, per);
-        add(0, PASS_W, (g.w1 - g.w0) * spb, per);
-        if (g.smin >= 0) add(1, PASS_L, g.l_units, per);
+        // lattice kernels on bitmaps: wave and layer passes in the launch of a
+        // leaner kernel beside the others (bitmap layer passes do not read
+        // the wave's tables); hash tables: the layer pass probes the wave's
+        // sector table, so it runs in the launch after the wave pass
+        const bool lattice_bitmap = g.kind == 0 && (g.dense & 2) != 0;
+        add(LIST_EVAL_A, PASS_B, spb, per);
+        add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_W, (g.w1 - g.w0) * spb, per);
+        if (g.smin >= 0) add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_B, PASS_L, g.l_units, per);
         for (int t = 0; t < N_TABLES; t++)
-            if (table_used(g.tab[t])) add(2, t, table_units(g.tab[t]), 1 << 16);
+            if (table_used(g.tab[t])) add(LIST_COUNT, t, table_units(g.tab[t]), 1 << 16);
     }
     RoundDesc rd;
     std::memset(&rd, 0, sizeof(rd));
     rd.fill_bytes = used;
-    for (int w = 0; w < 3; w++) {
+    for (int w = 0; w < N_LISTS; w++) {
         rd.items[w] = items[w];
         rd.first[w] = (int32_t)all.size();
         rd.n_work[w] = counts[w] = (int32_t)lists[w].size();
@@ -910,20 +947,20 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
     } else {
         DevTables t = dev_tables(c, nullptr, 0);
         HIP_TRY(launch_round_fill(c->arena, c->d_rd.p, groups, c->rs));
-        if (counts[0]) HIP_TRY(launch_eval(c->d_work.p, c->d_rd.p, 0, t, c->lds_slots, groups, c->rs));
-        if (counts[1]) HIP_TRY(launch_eval(c->d_work.p, c->d_rd.p, 1, t, c->lds_slots, groups, c->rs));
+        HIP_TRY(launch_branches(c, t, groups, counts));
     }
     hipEvent_t e1 = c->round_events.mark(c->rs);
     if (use_graph) {
         HIP_TRY(hipGraphLaunch(c->graph_exec[1], c->rs));
-    } else if (counts[2]) {
+    } else if (counts[LIST_COUNT]) {
         HIP_TRY(launch_count(c->d_work.p, c->d_rd.p, groups, c->rs));
     }
     hipEvent_t e2 = c->round_events.mark(c->rs);
     // the host reuses the work list, the round descriptor and the arena next round
     HIP_TRY(hipStreamSynchronize(c->rs));
     c->last_rounds++;
-    c->last_launches += use_graph ? 2 : (counts[0] ? 1 : 0) + (counts[1] ? 1 : 0);
+    c->last_launches += use_graph ? 3 : (counts[LIST_EVAL_A] ? 1 : 0) + (counts[LIST_EVAL_B] ? 1 : 0) +
+                                            (counts[LIST_EVAL_DL] ? 1 : 0);
     float ev = elapsed(e0, e1);
     *eval_ms += ev;
     *count_ms += elapsed(e1, e2);

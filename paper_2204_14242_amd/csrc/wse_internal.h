@@ -142,11 +142,20 @@ struct WorkEntry {
 
 // sizes of one arena round, read by the round's kernels from device memory so
 // that one captured graph serves every round
+// work lists of a round, one per launch
+enum {
+    LIST_EVAL_A = 0,   // block passes; wave passes except those of LIST_EVAL_DL
+    LIST_EVAL_B = 1,   // layer passes except those of LIST_EVAL_DL (after LIST_EVAL_A)
+    LIST_EVAL_DL = 2,  // wave and layer passes of lattice kernels on bitmaps (beside the others)
+    LIST_COUNT = 3,    // counting of every table
+    N_LISTS = 4
+};
+
 struct RoundDesc {
-    int64_t fill_bytes;   // arena bytes to clear
-    int64_t items[3];     // work items: evaluation (block+wave), evaluation (layers), counting
-    int32_t first[3];     // first work entry of each launch
-    int32_t n_work[3];    // work entries of each launch
+    int64_t fill_bytes;        // arena bytes to clear
+    int64_t items[N_LISTS];    // work items of each list
+    int32_t first[N_LISTS];    // first work entry of each list
+    int32_t n_work[N_LISTS];   // work entries of each list
 };
 
 struct Result {  // identical layout to wse_result

@@ -1293,8 +1293,12 @@ __device__ __forceinline__ const void* readfirstlane_ptr(const void* p)
 }
 
 // Evaluation kernel: resident workgroups loop over the round's work items;
-// the four waves of a workgroup share two LDS hash sets of lds_slots
-// entries and cooperate on one item at a time.
+// the four waves of a workgroup share the LDS (two hash sets of lds_slots
+// entries, or a cache of 2 * lds_slots bitmap words) and cooperate on one
+// item at a time.  LATTICE_BITMAP instantiates only the wave and layer
+// passes of lattice kernels on bitmaps, the bulk of the work, which then run
+// with fewer registers and more waves per SIMD.
+template <bool LATTICE_BITMAP>
 __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work_all,
                                               const RoundDesc* __restrict__ rd, int which, DevTables t,
                                               int lds_slots)
@@ -1338,6 +1342,11 @@ __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work
         P.err = 0;
         P.wtab = lds;
         P.wlog = llog + 1;
+        if (LATTICE_BITMAP) {
+            if (pass == PASS_W) run_pass<PASS_W, 0, true>(P, cc, c.w0, j0, j1);
+            else run_pass<PASS_L, 0, true>(P, cc, c.smin, j0, j1);
+            continue;
+        }
         const int dense_bits = __builtin_amdgcn_readfirstlane(c.dense);
         const bool dense = (dense_bits & (pass == PASS_B ? 1 : 2)) != 0;
         if (c.kind == 0) {
@@ -1372,8 +1381,12 @@ size_t eval_lds_bytes(int lds_slots)
 hipError_t launch_eval(const WorkEntry* work, const RoundDesc* rd, int which, DevTables t, int lds_slots,
                        int64_t groups, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_eval, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup), eval_lds_bytes(lds_slots), s,
-                       work, rd, which, t, lds_slots);
+    if (which == LIST_EVAL_DL)
+        hipLaunchKernelGGL(k_eval<true>, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup),
+                           eval_lds_bytes(lds_slots), s, work, rd, which, t, lds_slots);
+    else
+        hipLaunchKernelGGL(k_eval<false>, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup),
+                           eval_lds_bytes(lds_slots), s, work, rd, which, t, lds_slots);
     return hipGetLastError();
 }
 
@@ -1382,9 +1395,9 @@ hipError_t launch_eval(const WorkEntry* work, const RoundDesc* rd, int which, De
 __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ work_all,
                                                const RoundDesc* __restrict__ rd)
 {
-    const WorkEntry* work = work_all + rd->first[2];
-    const int n_work = rd->n_work[2];
-    const int64_t n_items = rd->items[2];
+    const WorkEntry* work = work_all + rd->first[LIST_COUNT];
+    const int n_work = rd->n_work[LIST_COUNT];
+    const int64_t n_items = rd->items[LIST_COUNT];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = lane_id();
     const int64_t n_waves = (int64_t)gridDim.x * kWavesPerGroup;
