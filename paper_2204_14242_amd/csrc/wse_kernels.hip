@@ -714,6 +714,23 @@ __device__ __forceinline__ const WorkEntry* find_entry(const WorkEntry* work, in
 __device__ __forceinline__ int64_t warp_distinct(bool valid, int64_t v, int log2ws)
 {
     uint64_t rem = __ballot(valid);
+    if (rem == 0) return 0;
+    // When the valid lanes are contiguous and their values never fall from
+    // one lane to the next inside a modelled warp (always so for lattice
+    // kernels, whose addresses rise with the thread index), equal values
+    // are runs and the count is the number of run starts.
+    {
+        const int lane = lane_id();
+        const uint32_t plo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, 0x138, 0xf, 0xf, true);
+        const uint32_t phi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)((uint64_t)v >> 32), 0x138, 0xf,
+                                                                0xf, true);
+        const int64_t pv = (int64_t)(((uint64_t)phi << 32) | plo);  // lane - 1 (wave_shr:1)
+        const int first = __builtin_ctzll(rem);
+        const uint64_t rem0 = rem >> first;
+        const bool start = (lane & ((1 << log2ws) - 1)) == 0 || lane == first;
+        if ((rem0 & (rem0 + 1)) == 0 && __ballot(valid && !start && v < pv) == 0)
+            return __popcll(__ballot(valid && (start || v != pv)));
+    }
     int64_t cnt = 0;
     uint64_t wmask1 = log2ws >= 6 ? ~0ull : ((1ull << (1 << log2ws)) - 1);
     while (rem) {
