@@ -915,7 +915,12 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
         // sector table, so it runs in the launch after the wave pass
         const bool lattice_bitmap = g.kind == 0 && (g.dense & 2) != 0;
         add(LIST_EVAL_A, PASS_B, spb, per);
-        add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_W, (g.w1 - g.w0) * spb, per);
+        add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_W, g.w_units, per);
+        // the warp-level store counts of the wave evaluate store instructions only
+        const int n_st = std::max(1, g.E - g.n_ld);
+        int64_t per_st = std::max<int64_t>(1, c->target_evals / ((int64_t)kLanes * n_st));
+        per_st = (per_st + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
+        if (g.E > g.n_ld) add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_WS, (g.w1 - g.w0) * spb, per_st);
         if (g.smin >= 0) add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_B, PASS_L, g.l_units, per);
         for (int t = 0; t < N_TABLES; t++)
             if (table_used(g.tab[t])) add(LIST_COUNT, t, table_units(g.tab[t]), 1 << 16);

@@ -11,7 +11,10 @@ namespace wse {
 // hash tables of one configuration
 enum { T_BSEC = 0, T_BLINE = 1, T_WSEC = 2, T_WLINE = 3, T_LLINE = 4, N_TABLES = 5 };
 // thread sets evaluated for one configuration
-enum { PASS_B = 0, PASS_W = 1, PASS_L = 2 };
+enum { PASS_B = 0, PASS_W = 1, PASS_L = 2, PASS_WS = 3 };
+// PASS_W and PASS_L take their blocks' threads in row order and fill the
+// sets; PASS_WS takes the wave's threads warp by warp for the warp-level
+// store sectors of the wave
 // insert semantics of a table entry's payload bits
 enum { MODE_SET = 0, MODE_OR = 1, MODE_MAX = 2 };
 
@@ -113,6 +116,7 @@ struct Cfg {
     int64_t sy, sz, g;
     int64_t evals[3];           // thread x instruction evaluations per pass (upper bound)
     int64_t l_units;            // layer pass: segments of its blocks' threads in row order
+    int64_t w_units;            // wave pass: segments of its blocks' threads in row order
     TableDesc tab[N_TABLES];
     int64_t table_bytes;        // arena bytes this configuration needs
 };

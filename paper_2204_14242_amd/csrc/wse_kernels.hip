@@ -544,6 +544,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
     c.evals[PASS_W] = (c.w1 - c.w0) * c.P * c.E;
     c.evals[PASS_L] = nL * c.P * c.E;
     c.l_units = nL > 0 ? row_order(c, c.smin, c.w0).units : 0;
+    c.w_units = c.w1 > c.w0 ? row_order(c, c.w0, c.w1).units : 0;
     c.tag_bits = bits_for((uint64_t)(nL + 1));
     const Expansion* X = S.kind == 0 ? &t.expansions[c.expansion_id] : nullptr;
     int bad = 0;
@@ -1075,8 +1076,9 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     const int64_t smin = c.smin;
     const int tag_bits = c.tag_bits;
     int64_t acc_up_ld = 0, acc_up_st = 0, acc_cyc = 0, acc_lanes = 0, acc_warps = 0;
+    constexpr bool ROW = PASS == PASS_W || PASS == PASS_L;  // row order
     const TableDesc& TS = c.tab[PASS == PASS_B ? T_BSEC : T_WSEC];
-    const TableDesc& TL = c.tab[PASS == PASS_W ? T_WLINE : (PASS == PASS_B ? T_BLINE : T_LLINE)];
+    const TableDesc& TL = c.tab[PASS == PASS_L ? T_LLINE : (PASS == PASS_B ? T_BLINE : T_WLINE)];
     const int sec_pb = PASS == PASS_W ? 2 : (PASS == PASS_L ? tag_bits : 0);
     const int line_pb = PASS == PASS_L ? tag_bits : 0;
     const int sec_mode = PASS == PASS_W ? MODE_OR : (PASS == PASS_L ? MODE_MAX : MODE_SET);
@@ -1090,9 +1092,10 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     const uint32_t off_s = (uint32_t)((PASS == PASS_L ? TS.tag_off : TS.off) >> 2);
     const uint32_t off_l = (uint32_t)(TL.off >> 2);
     const uint32_t words_s = (uint32_t)TS.words, words_l = (uint32_t)TL.words;
-    // layer pass: row order of its blocks; band thresholds in recency order
+    // wave and layer passes: row order of their blocks; layer band
+    // thresholds in recency order
     RowOrder ro;
-    if (PASS == PASS_L) ro = row_order(c, c.smin, c.w0);
+    if (ROW) ro = PASS == PASS_L ? row_order(c, c.smin, c.w0) : row_order(c, c.w0, c.w1);
     const int64_t s_band[2] = {c.n_order > 0 ? c.s[c.order[0]] : 0, c.n_order > 1 ? c.s[c.order[1]] : 0};
 
     for (int e0 = 0; e0 < E; e0 += kLanes) {
@@ -1113,7 +1116,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             if (DENSE && !seg_ok) break;
             int64_t tx, ty, tz, gx, gy, gz, kcur, bcur[3];
             bool valid;
-            if (PASS == PASS_L) {
+            if (ROW) {
                 // row order: 64 consecutive x of one thread row
                 int64_t r, x0, xe;
                 row_unit(ro, c, seg_ok ? jg + P.wave : 0, &r, &ty, &tz, &x0, &xe);
@@ -1157,7 +1160,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                     }
                 }
             }
-            if (e0 == 0 && seg_ok) {
+            if (e0 == 0 && seg_ok && PASS != PASS_WS) {
                 acc_lanes += __popcll(vmask);
                 if (PASS == PASS_B) {
                     const int ws = 1 << log2_warp;
@@ -1188,6 +1191,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                     const int64_t S = readlane64(ic.S, q);
                     const int32_t m = readlane32(meta, q);
                     const int st = m & 1;
+                    if (PASS == PASS_WS && !st) continue;
                     int64_t addr;
                     if (KIND == 0) {
                         addr = uelem ? ubase + S : base * (int64_t)(m >> 1) + S;
@@ -1222,8 +1226,9 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                                 new1 = lds_add(P, P.set1, kl, 0, MODE_SET);
                             }
                         }
-                    } else if (PASS == PASS_W) {
+                    } else if (PASS == PASS_WS) {
                         if (st) acc_up_st += warp_distinct(valid, sec, log2_warp);
+                    } else if (PASS == PASS_W) {
                         bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
                         if (__ballot(valid && !ok)) P.err |= 1;
                         bool act = valid && ok;
@@ -1293,6 +1298,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             atomicAdd(&ctr->l1_cycles_B, (unsigned long long)acc_cyc);
         } else if (PASS == PASS_W) {
             atomicAdd(&ctr->lanes_W, (unsigned long long)acc_lanes);
+        } else if (PASS == PASS_WS) {
             atomicAdd(&ctr->up_st_W, (unsigned long long)acc_up_st);
         } else {
             atomicAdd(&ctr->lanes_L, (unsigned long long)acc_lanes);
@@ -1361,11 +1367,18 @@ __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work
         P.wlog = llog + 1;
         if (LATTICE_BITMAP) {
             if (pass == PASS_W) run_pass<PASS_W, 0, true>(P, cc, c.w0, j0, j1);
+            else if (pass == PASS_WS) run_pass<PASS_WS, 0, true>(P, cc, c.w0, j0, j1);
             else run_pass<PASS_L, 0, true>(P, cc, c.smin, j0, j1);
             continue;
         }
         const int dense_bits = __builtin_amdgcn_readfirstlane(c.dense);
         const bool dense = (dense_bits & (pass == PASS_B ? 1 : 2)) != 0;
+        if (pass == PASS_WS) {
+            // warp-level store counts only: no sets, no synchronisation
+            if (c.kind == 0) run_pass<PASS_WS, 0, true>(P, cc, c.w0, j0, j1);
+            else run_pass<PASS_WS, 1, true>(P, cc, c.w0, j0, j1);
+            continue;
+        }
         if (c.kind == 0) {
             if (dense) {
                 if (pass == PASS_B) run_pass<PASS_B, 0, true>(P, cc, c.kB, j0, j1);
