@@ -270,15 +270,18 @@ wse_status wse_rhat(wse_ctx* ctx, const wse_fit* fit, const double* O, double* R
 /* Device time in milliseconds of each stage of the last wse_estimate call
  * on this context, measured with HIP events on the call's stream: [0]
  * expand+decode (including the host read-back of the plan), [1] evaluation
- * kernels, [2] counting kernels, [3] model+rank.  `n` entries (<= 8) are
- * copied. */
+ * kernels, [2] counting kernels, [3] model+rank, [4] the lattice bitmap
+ * evaluation launches alone (wave and layer passes of lattice kernels whose
+ * sets are bitmaps; they run beside the other evaluation launches, measured
+ * on their own stream).  `n` entries (<= 8) are copied. */
 wse_status wse_last_timings(const wse_ctx* ctx, double* ms, int32_t n);
 
 /* Work statistics of the last wse_estimate call on this context (n <= 8
  * entries): [0] (thread, instruction) address evaluations performed over all
  * thread sets, [1] table bytes used (hash tables and bitmaps), [2]
  * evaluation-kernel launches, [3] arena rounds, [4] configurations
- * evaluated, [5] configurations with sets kept as bitmaps. */
+ * evaluated, [5] configurations with sets kept as bitmaps, [6] evaluations
+ * performed by the lattice bitmap launches, [7] their number. */
 wse_status wse_last_stats(wse_ctx* ctx, int64_t* stats, int32_t n);
 
 /* Address evaluations the last wse_estimate call performed for each of its

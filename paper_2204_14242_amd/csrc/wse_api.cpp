@@ -115,7 +115,10 @@ bool is_device_ptr(const void* p)
 float elapsed(hipEvent_t a, hipEvent_t b)
 {
     float ms = 0.f;
-    if (a && b) (void)hipEventElapsedTime(&ms, a, b);
+    if (a && b && hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();  // leave no error behind for the next launch check
+        ms = 0.f;
+    }
     return ms;
 }
 
@@ -213,9 +216,14 @@ struct wse_ctx {
     hipStream_t rs = nullptr;  // stream of the round launches
     hipStream_t rs2 = nullptr;  // second branch of a round: layer passes of lattice kernels on bitmaps
     hipEvent_t fork = nullptr, join = nullptr;  // between the two branches
+    hipEvent_t dl_t0 = nullptr, dl_t1 = nullptr;  // around the lattice bitmap launch (timing)
+    double last_dl_ms = 0;        // lattice bitmap launches of the last call: time, launches
+    int64_t last_dl_launches = 0;
     // captured round graphs: [0] clear + evaluation launches, [1] counting
-    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
-    hipGraph_t graph[2] = {nullptr, nullptr};
+    // round graphs: clear, general evaluation launches, lattice bitmap launch, count
+    enum { G_FILL = 0, G_GEN = 1, G_DL = 2, G_COUNT = 3, N_GRAPHS = 4 };
+    hipGraphExec_t graph_exec[N_GRAPHS] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t graph[N_GRAPHS] = {nullptr, nullptr, nullptr, nullptr};
     const void* graph_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     int64_t graph_groups = 0;
     int graph_lds = 0;
@@ -233,6 +241,7 @@ struct wse_ctx {
     int64_t last_total = 0, last_table_bytes = 0, last_launches = 0, last_rounds = 0, last_dense = 0;
     std::vector<Counters> last_ctr;
     std::vector<int32_t> last_E;
+    std::vector<uint8_t> last_dl;  // configuration ran its wave and layer passes in the lattice bitmap launch
     wse_server* server = nullptr;
 };
 
@@ -300,7 +309,11 @@ wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out)
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->rs2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&c->dl_t0);
+    if (e == hipSuccess) e = hipEventCreate(&c->dl_t1);
     if (e != hipSuccess) {
+        if (c->dl_t1) (void)hipEventDestroy(c->dl_t1);
+        if (c->dl_t0) (void)hipEventDestroy(c->dl_t0);
         if (c->join) (void)hipEventDestroy(c->join);
         if (c->fork) (void)hipEventDestroy(c->fork);
         if (c->rs2) (void)hipStreamDestroy(c->rs2);
@@ -336,10 +349,12 @@ void wse_ctx_destroy(wse_ctx* c)
     c->d_jobs.release();
     c->d_work.release();
     c->d_rd.release();
-    for (int g = 0; g < 2; g++) {
+    for (int g = 0; g < wse_ctx::N_GRAPHS; g++) {
         if (c->graph_exec[g]) (void)hipGraphExecDestroy(c->graph_exec[g]);
         if (c->graph[g]) (void)hipGraphDestroy(c->graph[g]);
     }
+    if (c->dl_t1) (void)hipEventDestroy(c->dl_t1);
+    if (c->dl_t0) (void)hipEventDestroy(c->dl_t0);
     if (c->join) (void)hipEventDestroy(c->join);
     if (c->fork) (void)hipEventDestroy(c->fork);
     if (c->rs2) (void)hipStreamDestroy(c->rs2);
@@ -820,21 +835,37 @@ static void form_round(wse_ctx* c, const std::vector<Job*>& jobs, std::vector<Ro
     }
 }
 
-// The evaluation launches of a round as two branches that fork after the
-// clearing launch queued on the round stream and join back into it: the
-// general launches on the round stream, the lattice bitmap launch on the
-// second stream.  The lattice bitmap layer passes read nothing the general
-// launches write, and the block passes (few, long work items) leave most of
-// the device to them.
-static hipError_t launch_branches(wse_ctx* c, DevTables t, int64_t groups, const int32_t* counts = nullptr)
+// A round's launches on the round stream `rs` and, for the lattice bitmap
+// launch, the second stream `rs2`: clear; then two branches that fork after
+// the clear and join before counting: the general evaluation launches
+// (block passes and hash wave passes, then hash layer passes, which probe
+// the wave's sector tables) on rs, and the lattice bitmap launch on rs2,
+// between the two timing events.  The lattice bitmap passes read nothing
+// the general launches write, and the block passes (few, long work items)
+// leave most of the device to them.  Each piece is one captured graph when
+// `use_graph`, else launched directly (skipping empty lists).
+static hipError_t launch_round(wse_ctx* c, DevTables t, int64_t groups, bool use_graph, const int32_t* counts)
 {
-    hipError_t e = hipEventRecord(c->fork, c->rs);
+    auto piece = [&](int g, hipStream_t s, auto direct) -> hipError_t {
+        return use_graph ? hipGraphLaunch(c->graph_exec[g], s) : direct();
+    };
+    hipError_t e = piece(wse_ctx::G_FILL, c->rs, [&] { return launch_round_fill(c->arena, c->d_rd.p, groups, c->rs); });
+    if (e == hipSuccess) e = hipEventRecord(c->fork, c->rs);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->rs2, c->fork, 0);
-    if (e == hipSuccess && (!counts || counts[LIST_EVAL_DL]))
-        e = launch_eval(c->d_work.p, c->d_rd.p, LIST_EVAL_DL, t, c->lds_slots, groups, c->rs2);
+    if (e == hipSuccess) e = hipEventRecord(c->dl_t0, c->rs2);
+    if (e == hipSuccess && (use_graph || counts[LIST_EVAL_DL]))
+        e = piece(wse_ctx::G_DL, c->rs2, [&] {
+            return launch_eval(c->d_work.p, c->d_rd.p, LIST_EVAL_DL, t, c->lds_slots, groups, c->rs2);
+        });
+    if (e == hipSuccess) e = hipEventRecord(c->dl_t1, c->rs2);
     if (e == hipSuccess) e = hipEventRecord(c->join, c->rs2);
-    for (int w = LIST_EVAL_A; w <= LIST_EVAL_B && e == hipSuccess; w++)
-        if (!counts || counts[w]) e = launch_eval(c->d_work.p, c->d_rd.p, w, t, c->lds_slots, groups, c->rs);
+    if (e == hipSuccess)
+        e = piece(wse_ctx::G_GEN, c->rs, [&] {
+            hipError_t r = hipSuccess;
+            for (int w = LIST_EVAL_A; w <= LIST_EVAL_B && r == hipSuccess; w++)
+                if (counts[w]) r = launch_eval(c->d_work.p, c->d_rd.p, w, t, c->lds_slots, groups, c->rs);
+            return r;
+        });
     if (e == hipSuccess) e = hipStreamWaitEvent(c->rs, c->join, 0);
     return e;
 }
@@ -848,28 +879,27 @@ static wse_status ensure_round_graphs(wse_ctx* c, int64_t groups)
     bool same = c->graph_exec[0] && c->graph_groups == groups && c->graph_lds == c->lds_slots;
     for (int i = 0; i < 6 && same; i++) same = key[i] == c->graph_key[i];
     if (same) return WSE_OK;
-    for (int g = 0; g < 2; g++) {
+    for (int g = 0; g < wse_ctx::N_GRAPHS; g++) {
         if (c->graph_exec[g]) (void)hipGraphExecDestroy(c->graph_exec[g]);
         if (c->graph[g]) (void)hipGraphDestroy(c->graph[g]);
         c->graph_exec[g] = nullptr;
         c->graph[g] = nullptr;
     }
-    // graph 0: clear the round's tables, then two branches: the general
-    // evaluation launches (block and wave passes, then the layer passes on
-    // hash tables) and, beside them, the lattice bitmap launch
-    HIP_TRY(hipStreamBeginCapture(c->rs, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_round_fill(c->arena, c->d_rd.p, groups, c->rs);
-    if (e == hipSuccess) e = launch_branches(c, t, groups);
-    hipError_t e2 = hipStreamEndCapture(c->rs, &c->graph[0]);
-    if (e != hipSuccess || e2 != hipSuccess)
-        return fail(WSE_EDEVICE, std::string("round graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
-    // graph 1: count the round's tables
-    HIP_TRY(hipStreamBeginCapture(c->rs, hipStreamCaptureModeThreadLocal));
-    e = launch_count(c->d_work.p, c->d_rd.p, groups, c->rs);
-    e2 = hipStreamEndCapture(c->rs, &c->graph[1]);
-    if (e != hipSuccess || e2 != hipSuccess)
-        return fail(WSE_EDEVICE, std::string("count graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
-    for (int g = 0; g < 2; g++) HIP_TRY(hipGraphInstantiate(&c->graph_exec[g], c->graph[g], nullptr, nullptr, 0));
+    for (int g = 0; g < wse_ctx::N_GRAPHS; g++) {
+        hipStream_t s = g == wse_ctx::G_DL ? c->rs2 : c->rs;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        if (g == wse_ctx::G_FILL) e = launch_round_fill(c->arena, c->d_rd.p, groups, s);
+        if (g == wse_ctx::G_GEN)
+            for (int w = LIST_EVAL_A; w <= LIST_EVAL_B && e == hipSuccess; w++)
+                e = launch_eval(c->d_work.p, c->d_rd.p, w, t, c->lds_slots, groups, s);
+        if (g == wse_ctx::G_DL) e = launch_eval(c->d_work.p, c->d_rd.p, LIST_EVAL_DL, t, c->lds_slots, groups, s);
+        if (g == wse_ctx::G_COUNT) e = launch_count(c->d_work.p, c->d_rd.p, groups, s);
+        hipError_t e2 = hipStreamEndCapture(s, &c->graph[g]);
+        if (e != hipSuccess || e2 != hipSuccess)
+            return fail(WSE_EDEVICE, std::string("round graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        HIP_TRY(hipGraphInstantiate(&c->graph_exec[g], c->graph[g], nullptr, nullptr, 0));
+    }
     for (int i = 0; i < 6; i++) c->graph_key[i] = key[i];
     c->graph_groups = groups;
     c->graph_lds = c->lds_slots;
@@ -947,16 +977,10 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
         HIP_TRY(hipMemcpyAsync(c->d_work.p, all.data(), all.size() * sizeof(WorkEntry), hipMemcpyHostToDevice, c->rs));
     HIP_TRY(hipMemcpyAsync(c->d_rd.p, &rd, sizeof(rd), hipMemcpyHostToDevice, c->rs));
     hipEvent_t e0 = c->round_events.mark(c->rs);
-    if (use_graph) {
-        HIP_TRY(hipGraphLaunch(c->graph_exec[0], c->rs));
-    } else {
-        DevTables t = dev_tables(c, nullptr, 0);
-        HIP_TRY(launch_round_fill(c->arena, c->d_rd.p, groups, c->rs));
-        HIP_TRY(launch_branches(c, t, groups, counts));
-    }
+    HIP_TRY(launch_round(c, dev_tables(c, nullptr, 0), groups, use_graph, counts));
     hipEvent_t e1 = c->round_events.mark(c->rs);
     if (use_graph) {
-        HIP_TRY(hipGraphLaunch(c->graph_exec[1], c->rs));
+        HIP_TRY(hipGraphLaunch(c->graph_exec[wse_ctx::G_COUNT], c->rs));
     } else if (counts[LIST_COUNT]) {
         HIP_TRY(launch_count(c->d_work.p, c->d_rd.p, groups, c->rs));
     }
@@ -968,6 +992,10 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
                                             (counts[LIST_EVAL_DL] ? 1 : 0);
     float ev = elapsed(e0, e1);
     *eval_ms += ev;
+    if (counts[LIST_EVAL_DL]) {
+        c->last_dl_ms += elapsed(c->dl_t0, c->dl_t1);
+        c->last_dl_launches++;
+    }
     *count_ms += elapsed(e1, e2);
     if (c->progress)
         fprintf(stderr, "[wsest] round %lld: %zu configurations, %.1f ms evaluation\n", (long long)c->last_rounds,
@@ -1003,6 +1031,8 @@ extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t 
     j.out = out;
     j.rank_out = rank_out;
     c->last_table_bytes = c->last_launches = c->last_rounds = 0;
+    c->last_dl_ms = 0;
+    c->last_dl_launches = 0;
     c->events.used = 0;
     hipEvent_t t0 = c->events.mark(st);
     wse_status s = job_prepare(c, j, st);
@@ -1035,13 +1065,17 @@ extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t 
         c->timings[1] = eval_ms;
         c->timings[2] = count_ms;
         c->timings[3] = elapsed(t2, t3);
+        c->timings[4] = c->last_dl_ms;
         c->last_total = j.total;
         c->last_ctr.resize(j.total);
         c->last_E.resize(j.total);
         c->last_dense = 0;
+        c->last_dl.resize(j.total);
         for (int64_t i = 0; i < j.total; i++) {
-            c->last_E[i] = j.cfgs[i].status == 0 ? j.cfgs[i].E : 0;
-            c->last_dense += j.cfgs[i].status == 0 && j.cfgs[i].dense != 0;
+            const Cfg& g = j.cfgs[i];
+            c->last_E[i] = g.status == 0 ? g.E : 0;
+            c->last_dense += g.status == 0 && g.dense != 0;
+            c->last_dl[i] = g.status == 0 && g.kind == 0 && (g.dense & 2) != 0;
         }
         hipError_t e = hipMemcpy(c->last_ctr.data(), j.d_ctr.p, j.total * sizeof(Counters), hipMemcpyDeviceToHost);
         if (e != hipSuccess) s = fail(WSE_EDEVICE, hipGetErrorString(e));
@@ -1057,8 +1091,12 @@ extern "C" wse_status wse_last_stats(wse_ctx* c, int64_t* stats, int32_t n)
     int64_t evals = 0;
     for (int64_t i = 0; i < c->last_total; i++)
         evals += (int64_t)(c->last_ctr[i].lanes_B + c->last_ctr[i].lanes_W + c->last_ctr[i].lanes_L) * c->last_E[i];
+    int64_t dl_evals = 0;
+    for (int64_t i = 0; i < c->last_total; i++)
+        if (c->last_dl[i])
+            dl_evals += (int64_t)(c->last_ctr[i].lanes_W + c->last_ctr[i].lanes_L) * c->last_E[i];
     int64_t v[8] = {evals, c->last_table_bytes, c->last_launches, c->last_rounds, c->last_total, c->last_dense,
-                    0, 0};
+                    dl_evals, c->last_dl_launches};
     for (int i = 0; i < n && i < 8; i++) stats[i] = v[i];
     return WSE_OK;
 }

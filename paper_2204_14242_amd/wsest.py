@@ -336,7 +336,8 @@ class Context:
         v = (C.c_int64 * 8)()
         _check(lib().wse_last_stats(self._ctx, v, 8), self._ctx)
         return {"evals": v[0], "table_bytes": v[1], "eval_launches": v[2], "rounds": v[3],
-                "configs": v[4], "bitmap_configs": v[5]}
+                "configs": v[4], "bitmap_configs": v[5], "lattice_bitmap_evals": v[6],
+                "lattice_bitmap_launches": v[7]}
 
     def last_evals(self, n):
         """address evaluations of each configuration of the last call"""
