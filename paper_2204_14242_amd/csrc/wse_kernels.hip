@@ -22,6 +22,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace wse {
 
 // ------------------------------------------------------------------ helpers
@@ -1022,6 +1024,30 @@ __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base,
     return r;
 }
 
+// word_probe for a step whose keys form runs: `base` is the same on every
+// lane, the active lanes (mask `am`) are one contiguous range and their keys
+// rise by 0 or 1 from lane to lane.  Then a run of equal words
+// holds every key between its ends, and its last lane forms the run's bits
+// from its own key and, in the first word, the first active lane's key,
+// with no scan.
+__device__ __forceinline__ WordProbe word_probe_runs(const PassCtx& P, uint32_t base, bool act, uint32_t key,
+                                                     uint64_t am)
+{
+    const int first = am ? __builtin_ctzll(am) : 0;
+    const uint32_t kfirst = (uint32_t)__builtin_amdgcn_readlane((int)key, first);
+    const uint32_t w1 = act ? base + (key >> 5) + 1 : 0xffffffffu;
+    const uint32_t wfirst1 = base + (kfirst >> 5) + 1;
+    const uint32_t nw1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x130, 0xf, 0xf, true);  // wave_shl:1
+    const bool lead = act && nw1 != w1;
+    const uint32_t lo = w1 == wfirst1 ? (kfirst & 31) : 0u;
+    WordProbe r;
+    r.k1 = lead ? w1 : 0u;
+    r.bits = (0xffffffffu >> (31 - (key & 31))) & (0xffffffffu << lo);
+    r.slot = (w1 * 0x9e3779b1u) >> (32 - P.wlog);
+    r.old = P.wtab[r.slot];
+    return r;
+}
+
 // Keeps the compiler from sinking the probes' slot reads into their commits,
 // so that the reads of one step are in flight together.
 __device__ __forceinline__ void probes_issued() { asm volatile("" ::: "memory"); }
@@ -1055,7 +1081,7 @@ __device__ __forceinline__ void word_commit(PassCtx& P, WordProbe r)
 // insert into the workgroup's shared LDS sets (the waves move in lockstep so
 // that the keys they share meet there); bitmap configurations set their bits
 // in HBM directly and need no synchronisation.
-template <int PASS, int KIND, bool DENSE>
+template <int PASS, int KIND, bool DENSE, bool RUNS = false>
 __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, int64_t j1)
 {
     const Cfg& c = *P.c;
@@ -1184,7 +1210,19 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             int64_t base = 0;
             if (KIND == 0) base = (gx + g) + sy * (f1 * gy + g) + sz * (f2 * gz + g);
             const int64_t ubase = uelem ? base * uelem : 0;
-
+            // Lattice kernels in row order with one element size: the lanes are
+            // consecutive x of one thread row, so addresses rise by the element
+            // size from lane to lane, and while the element fits a sector the
+            // keys of every set rise by 0 or 1 and the active lanes of every
+            // step form one range.  Such segments (on one layer band) take the
+            // run-end word probes; the instruction loop is instantiated for
+            // both kinds of segment.
+            bool seg_runs = RUNS && KIND == 0 && ROW && uelem > 0 && uelem <= ((int64_t)1 << ls);
+            if (RUNS && DENSE && PASS == PASS_L)
+                seg_runs = seg_runs &&
+                           __ballot(valid && band != (uint32_t)__builtin_amdgcn_readfirstlane((int)band)) == 0;
+            auto instructions = [&](auto runs_tag) {
+            constexpr bool FAST = decltype(runs_tag)::value;
             for (int q = 0; q < n_in; q++) {
                 int new0 = 0, new1 = 0;
                 if (vmask) {
@@ -1193,7 +1231,9 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                     const int st = m & 1;
                     if (PASS == PASS_WS && !st) continue;
                     int64_t addr;
-                    if (KIND == 0) {
+                    if (FAST) {
+                        addr = ubase + S;
+                    } else if (KIND == 0) {
                         addr = uelem ? ubase + S : base * (int64_t)(m >> 1) + S;
                     } else {
                         int64_t idx = 0;
@@ -1233,9 +1273,17 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         if (__ballot(valid && !ok)) P.err |= 1;
                         bool act = valid && ok;
                         if (DENSE) {
-                            WordProbe a = word_probe(P, bs + (st ? words_s : 0u), act,
-                                                     (uint32_t)(us + readlane64(ic.fs, q) - 1));
-                            WordProbe b = word_probe(P, bl, act, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
+                            const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
+                            const uint32_t kl = (uint32_t)(ul + readlane64(ic.fl, q) - 1);
+                            WordProbe a, b;
+                            if (FAST) {
+                                const uint64_t am = __ballot(act);
+                                a = word_probe_runs(P, bs + (st ? words_s : 0u), act, ks, am);
+                                b = word_probe_runs(P, bl, act, kl, am);
+                            } else {
+                                a = word_probe(P, bs + (st ? words_s : 0u), act, ks);
+                                b = word_probe(P, bl, act, kl);
+                            }
                             probes_issued();
                             word_commit(P, a);
                             word_commit(P, b);
@@ -1250,11 +1298,18 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         bool ok = (uint64_t)ul < (uint64_t)span_l;
                         if (__ballot(valid && !ok)) P.err |= 1;
                         if (DENSE) {
-                            WordProbe b = word_probe(P, bl, valid && ok, (uint32_t)(ul + readlane64(ic.fl, q) - 1));
-                            WordProbe a = {0ull, 0u, 0u, 0u};
-                            if (do_sec) {
-                                bool in = valid && (uint64_t)us < (uint64_t)span_s;
-                                a = word_probe(P, bs, in, (uint32_t)(us + readlane64(ic.fs, q) - 1));
+                            const bool actl = valid && ok;
+                            const bool in = do_sec && valid && (uint64_t)us < (uint64_t)span_s;
+                            const uint32_t kl = (uint32_t)(ul + readlane64(ic.fl, q) - 1);
+                            const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
+                            WordProbe a = {0ull, 0u, 0u, 0u}, b;
+                            if (FAST) {
+                                const uint64_t aml = __ballot(actl), ams = __ballot(in);
+                                b = word_probe_runs(P, bl, actl, kl, aml);
+                                if (ams) a = word_probe_runs(P, bs, in, ks, ams);
+                            } else {
+                                b = word_probe(P, bl, actl, kl);
+                                if (do_sec) a = word_probe(P, bs, in, ks);
                             }
                             probes_issued();
                             word_commit(P, b);
@@ -1274,6 +1329,13 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                     }
                 }
                 if (!DENSE) step_sync<PASS>(P, new0, new1, do_sec);
+            }
+            };
+            if constexpr (RUNS) {
+                if (seg_runs) instructions(std::true_type{});
+                else instructions(std::false_type{});
+            } else {
+                instructions(std::false_type{});
             }
         }
     }
@@ -1322,7 +1384,7 @@ __device__ __forceinline__ const void* readfirstlane_ptr(const void* p)
 // passes of lattice kernels on bitmaps, the bulk of the work, which then run
 // with fewer registers and more waves per SIMD.
 template <bool LATTICE_BITMAP>
-__global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work_all,
+__global__ __launch_bounds__(256, LATTICE_BITMAP ? 4 : 1) void k_eval(const WorkEntry* __restrict__ work_all,
                                               const RoundDesc* __restrict__ rd, int which, DevTables t,
                                               int lds_slots)
 {
@@ -1366,9 +1428,9 @@ __global__ __launch_bounds__(256) void k_eval(const WorkEntry* __restrict__ work
         P.wtab = lds;
         P.wlog = llog + 1;
         if (LATTICE_BITMAP) {
-            if (pass == PASS_W) run_pass<PASS_W, 0, true>(P, cc, c.w0, j0, j1);
+            if (pass == PASS_W) run_pass<PASS_W, 0, true, true>(P, cc, c.w0, j0, j1);
             else if (pass == PASS_WS) run_pass<PASS_WS, 0, true>(P, cc, c.w0, j0, j1);
-            else run_pass<PASS_L, 0, true>(P, cc, c.smin, j0, j1);
+            else run_pass<PASS_L, 0, true, true>(P, cc, c.smin, j0, j1);
             continue;
         }
         const int dense_bits = __builtin_amdgcn_readfirstlane(c.dense);
