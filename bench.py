@@ -201,12 +201,12 @@ def main():
     # events on its own stream; the whole evaluation phase for context
     phase = OPS_PER_EVAL * evals / (eval_ms / 1e3) / 1e12 if eval_ms > 0 else 0.0
     if dl_launches > 0 and dl_ms > 0:
-        kernel = "k_eval<true> (wave and layer passes of lattice kernels on bitmaps)"
+        kname = "k_eval<true> (wave and layer passes of lattice kernels on bitmaps)"
         achieved = OPS_PER_EVAL * dl_evals / (dl_ms / 1e3) / 1e12
         avg_ms = dl_ms / dl_launches
         per_launch = OPS_PER_EVAL * dl_evals / dl_launches
     else:
-        kernel = "k_eval (all evaluation launches of a round)"
+        kname = "k_eval (all evaluation launches of a round)"
         achieved = phase
         avg_ms = eval_ms / max(st["rounds"] * a.steps, 1)
         per_launch = OPS_PER_EVAL * evals / max(st["rounds"] * a.steps, 1)
@@ -228,7 +228,7 @@ def main():
                    "eval_launches_per_step": st["eval_launches"], "arena_rounds": st["rounds"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "kernel": kernel, "avg_launch_ms": avg_ms, "lane_ops_per_launch": per_launch,
+                     "kernel": kname, "avg_launch_ms": avg_ms, "lane_ops_per_launch": per_launch,
                      "ops_per_eval": OPS_PER_EVAL,
                      "evaluation_phase": {"achieved": phase, "frac": phase / VALU_PEAK_TOPS,
                                           "ms_per_step": eval_ms / a.steps}},
