@@ -210,6 +210,11 @@ typedef struct {
                                    group has a key range of at most 2^bitmap_log2 times the
                                    evaluations that reach it (and below 2^32 keys); 0 = always
                                    hash tables (0 .. 8) */
+    int32_t row_ranges;         /* 1: lattice kernels on bitmaps whose element fits a sector fill
+                                   the wave and layer sets from the address range each instruction
+                                   covers along a whole thread row, instead of evaluating every
+                                   (thread, instruction) pair; same results; 0 = evaluate (0, 1) */
+    int32_t pad;                /* 0 */
 } wse_tuning;
 
 wse_status wse_get_tuning(wse_ctx* ctx, wse_tuning* tuning);

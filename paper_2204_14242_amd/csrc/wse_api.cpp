@@ -231,6 +231,7 @@ struct wse_ctx {
     int lds_slots = 2048;
     int table_slack = 1;
     int bitmap_log2 = 5;
+    int row_ranges = 0;
     int groups_per_cu = 16;
     int64_t target_evals = 1 << 19;
     bool dirty_kernels = false, dirty_hws = false;
@@ -944,14 +945,22 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
         // the wave's tables); hash tables: the layer pass probes the wave's
         // sector table, so it runs in the launch after the wave pass
         const bool lattice_bitmap = g.kind == 0 && (g.dense & 2) != 0;
+        // row ranges: lattice bitmap passes whose element fits a sector
+        const bool rows = c->row_ranges && lattice_bitmap && g.uniform_elem > 0 &&
+                          g.uniform_elem <= c->hws[g.hw_id].sector_bytes;
+        const int64_t row_len = std::max<int64_t>(1, g.T[0]);
+        int64_t per_rows = std::max<int64_t>(1, c->target_evals / (row_len * std::max(1, g.E)));
+        per_rows = (per_rows + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
         add(LIST_EVAL_A, PASS_B, spb, per);
-        add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_W, g.w_units, per);
+        if (rows) add(LIST_EVAL_DL, PASS_WR, g.w_rows, per_rows);
+        else add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_W, g.w_units, per);
         // the warp-level store counts of the wave evaluate store instructions only
         const int n_st = std::max(1, g.E - g.n_ld);
         int64_t per_st = std::max<int64_t>(1, c->target_evals / ((int64_t)kLanes * n_st));
         per_st = (per_st + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
         if (g.E > g.n_ld) add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_WS, (g.w1 - g.w0) * spb, per_st);
-        if (g.smin >= 0) add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_B, PASS_L, g.l_units, per);
+        if (g.smin >= 0 && rows) add(LIST_EVAL_DL, PASS_LR, g.l_rows, per_rows);
+        else if (g.smin >= 0) add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_B, PASS_L, g.l_units, per);
         for (int t = 0; t < N_TABLES; t++)
             if (table_used(g.tab[t])) add(LIST_COUNT, t, table_units(g.tab[t]), 1 << 16);
     }
@@ -1156,6 +1165,8 @@ static wse_status check_tuning(const wse_ctx* c, const wse_tuning* t)
     if (t->item_evals < (1 << 12) || t->item_evals > (1 << 22)) return fail(WSE_EINVAL, "item_evals must be 2^12..2^22");
     if (t->groups_per_cu < 1 || t->groups_per_cu > 64) return fail(WSE_EINVAL, "groups_per_cu must be 1..64");
     if (t->bitmap_log2 < 0 || t->bitmap_log2 > 8) return fail(WSE_EINVAL, "bitmap_log2 must be 0..8");
+    if (t->row_ranges != 0 && t->row_ranges != 1) return fail(WSE_EINVAL, "row_ranges must be 0 or 1");
+    if (t->pad != 0) return fail(WSE_EINVAL, "pad must be 0");
     return WSE_OK;
 }
 
@@ -1166,6 +1177,8 @@ static void get_tuning(const wse_ctx* c, wse_tuning* t)
     t->item_evals = c->target_evals;
     t->groups_per_cu = c->groups_per_cu;
     t->bitmap_log2 = c->bitmap_log2;
+    t->row_ranges = c->row_ranges;
+    t->pad = 0;
 }
 
 static void put_tuning(wse_ctx* c, const wse_tuning* t)
@@ -1175,6 +1188,7 @@ static void put_tuning(wse_ctx* c, const wse_tuning* t)
     c->target_evals = t->item_evals;
     c->groups_per_cu = t->groups_per_cu;
     c->bitmap_log2 = t->bitmap_log2;
+    c->row_ranges = t->row_ranges;
 }
 
 extern "C" wse_status wse_get_tuning(wse_ctx* c, wse_tuning* t)

@@ -547,6 +547,13 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
     c.evals[PASS_L] = nL * c.P * c.E;
     c.l_units = nL > 0 ? row_order(c, c.smin, c.w0).units : 0;
     c.w_units = c.w1 > c.w0 ? row_order(c, c.w0, c.w1).units : 0;
+    {
+        const int64_t rows = (int64_t)c.b[1] * c.b[2];
+        RowOrder ow = row_order(c, c.w0, c.w1);
+        c.w_rows = c.w1 > c.w0 ? (ow.rl - ow.r0 + 1) * rows : 0;
+        RowOrder ol = nL > 0 ? row_order(c, c.smin, c.w0) : ow;
+        c.l_rows = nL > 0 ? (ol.rl - ol.r0 + 1) * rows : 0;
+    }
     c.tag_bits = bits_for((uint64_t)(nL + 1));
     const Expansion* X = S.kind == 0 ? &t.expansions[c.expansion_id] : nullptr;
     int bad = 0;
@@ -1075,6 +1082,125 @@ __device__ __forceinline__ void word_commit(PassCtx& P, WordProbe r)
     }
 }
 
+// Set the bits [k_lo, k_hi] (inclusive, k_lo <= k_hi) of the bitmap at word
+// offset `base` through the workgroup's word cache, one word at a time.
+__device__ __forceinline__ void set_key_range(PassCtx& P, uint32_t base, uint32_t k_lo, uint32_t k_hi)
+{
+    const uint32_t w_lo = k_lo >> 5, w_hi = k_hi >> 5;
+    for (uint32_t w = w_lo; w <= w_hi; w++) {
+        const uint32_t lo = w == w_lo ? (k_lo & 31) : 0u;
+        const uint32_t hi = w == w_hi ? (k_hi & 31) : 31u;
+        WordProbe r;
+        r.k1 = base + w + 1;
+        r.bits = (0xffffffffu >> (31 - hi)) & (0xffffffffu << lo);
+        r.slot = (r.k1 * 0x9e3779b1u) >> (32 - P.wlog);
+        r.old = P.wtab[r.slot];
+        word_commit(P, r);
+    }
+}
+
+// Wave or layer pass of a lattice kernel with one element size no larger
+// than a sector, on bitmaps, by row ranges.  Along one thread row the
+// threads are consecutive x, so one instruction's addresses over an x range
+// are one arithmetic progression with a step no larger than a sector: its
+// sectors, and its lines, are exactly the units between those of its first
+// and its last address.  The pass's units are the thread rows of its blocks
+// (row order); each lane takes one instruction of the row and sets the unit
+// ranges of the row's x range, split where the layer band changes.  The sets
+// are the same as when every (thread, instruction) pair is evaluated.
+template <int PASS>
+__device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, int64_t j1)
+{
+    const Cfg& c = *P.c;
+    const int lane = lane_id();
+    const int ls = P.H->log2_sector, ll = P.H->log2_line;
+    const int64_t nb0 = c.nb[0], nb1 = c.nb[1];
+    const int64_t b0 = c.b[0], b1 = c.b[1], b2 = c.b[2];
+    const int lb1 = c.lb[1];
+    const int64_t T0 = c.T[0], T1 = c.T[1], T2 = c.T[2];
+    const int64_t sy = c.sy, sz = c.sz, g = c.g, f1 = c.fold[1], f2 = c.fold[2];
+    const int64_t uelem = c.uniform_elem;
+    const TableDesc& TS = c.tab[T_WSEC];
+    const TableDesc& TL = c.tab[PASS == PASS_L ? T_LLINE : T_WLINE];
+    const bool do_sec = table_used(TS);
+    const int64_t umin_s = TS.umin, span_s = TS.span, umin_l = TL.umin, span_l = TL.span;
+    const uint32_t off_s = (uint32_t)((PASS == PASS_L ? TS.tag_off : TS.off) >> 2);
+    const uint32_t off_l = (uint32_t)(TL.off >> 2);
+    const uint32_t words_s = (uint32_t)TS.words, words_l = (uint32_t)TL.words;
+    const RowOrder ro = PASS == PASS_L ? row_order(c, c.smin, c.w0) : row_order(c, c.w0, c.w1);
+    const int64_t rows_per = b1 * b2;
+    const int n_order = c.n_order;
+    const int64_t s_band[2] = {n_order > 0 ? c.s[c.order[0]] : 0, n_order > 1 ? c.s[c.order[1]] : 0};
+    const int E = c.E;
+    int64_t acc_lanes = 0;
+    for (int e0 = 0; e0 < E; e0 += kLanes) {
+        const bool mine = e0 + lane < E;
+        IConst ic;
+        if (mine) ic = load_iconst<0>(P, e0 + lane, TS, TL);
+        else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}};
+        for (int64_t u = j0 + P.wave; u < j1; u += kWavesPerGroup) {
+            const int64_t r = ro.r0 + u / rows_per;
+            const int64_t tr = u % rows_per;
+            const int64_t gy = (r % nb1) * b1 + (tr & (b1 - 1));
+            const int64_t gz = (r / nb1) * b2 + (tr >> lb1);
+            const int64_t xa = r == ro.r0 ? ro.xa0 : 0;
+            const int64_t xe = r == ro.r0 ? ro.xb0 : (r == ro.rl ? ro.xbl : T0);
+            if (gy >= T1 || gz >= T2 || xa >= xe) continue;
+            if (e0 == 0) acc_lanes += xe - xa;
+            // x ranges of constant layer band: block k = x / b0 + nb0 * r
+            // reaches a set's start s from x = (s - nb0 * r) * b0 on
+            int64_t cut[3] = {xa, xa, xa};  // start of band 2, 1, 0 ranges
+            if (PASS == PASS_L) {
+                auto from = [&](int64_t sb) {
+                    int64_t x = (sb - nb0 * r) * b0;
+                    return x < xa ? xa : (x > xe ? xe : x);
+                };
+                cut[2] = n_order > 0 ? from(s_band[0]) : xa;
+                cut[1] = n_order > 1 ? from(s_band[1]) : xa;
+                if (n_order < 2) cut[1] = xa;
+            }
+            const int64_t rowbase = g + sy * (f1 * gy + g) + sz * (f2 * gz + g);
+            if (mine) {
+                for (int band = 0; band < (PASS == PASS_L ? n_order : 1); band++) {
+                    // band 0: [cut[2], xe); band 1: [cut[1], cut[2]); band 2: [xa, cut[1])
+                    const int64_t x0 = PASS == PASS_L ? (band == 0 ? cut[2] : (band == 1 ? cut[1] : xa)) : xa;
+                    const int64_t x1 = PASS == PASS_L ? (band == 0 ? xe : (band == 1 ? cut[2] : cut[1])) : xe;
+                    if (x0 >= x1) continue;
+                    const int64_t a_lo = (rowbase + x0) * uelem + ic.S;
+                    const int64_t a_hi = (rowbase + x1 - 1) * uelem + ic.S;
+                    const int64_t ul_lo = (a_lo >> ll) - umin_l, ul_hi = (a_hi >> ll) - umin_l;
+                    const int64_t us_lo = (a_lo >> ls) - umin_s, us_hi = (a_hi >> ls) - umin_s;
+                    if (ul_lo < 0 || ul_hi >= span_l || (PASS == PASS_W && (us_lo < 0 || us_hi >= span_s))) {
+                        P.err |= 1;
+                        continue;
+                    }
+                    set_key_range(P, off_l + (uint32_t)band * words_l, (uint32_t)(ul_lo + ic.fl - 1),
+                                  (uint32_t)(ul_hi + ic.fl - 1));
+                    if (PASS == PASS_W) {
+                        set_key_range(P, off_s + (ic.st ? words_s : 0u), (uint32_t)(us_lo + ic.fs - 1),
+                                      (uint32_t)(us_hi + ic.fs - 1));
+                    } else if (do_sec) {
+                        // layer sectors count only inside the wave's sector range
+                        const int64_t lo = us_lo < 0 ? 0 : us_lo, hi = us_hi >= span_s ? span_s - 1 : us_hi;
+                        if (lo <= hi)
+                            set_key_range(P, off_s + (uint32_t)band * words_s, (uint32_t)(lo + ic.fs - 1),
+                                          (uint32_t)(hi + ic.fs - 1));
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    flush_words(P);
+    __syncthreads();
+    const bool any_err = __ballot(P.err != 0) != 0;
+    if (lane == 0) {
+        if (PASS == PASS_W) atomicAdd(&ctr->lanes_W, (unsigned long long)acc_lanes);
+        else atomicAdd(&ctr->lanes_L, (unsigned long long)acc_lanes);
+        if (any_err) atomicOr(&ctr->err, 1ull);
+    }
+}
+
 // One pass (representative block, wave or layer interval) over the segments
 // [j0, j1) of 64 consecutive threads.  The workgroup's waves take
 // consecutive segments, one instruction per step.  Hash configurations
@@ -1430,6 +1556,8 @@ __global__ __launch_bounds__(256, LATTICE_BITMAP ? 4 : 1) void k_eval(const Work
         if (LATTICE_BITMAP) {
             if (pass == PASS_W) run_pass<PASS_W, 0, true, true>(P, cc, c.w0, j0, j1);
             else if (pass == PASS_WS) run_pass<PASS_WS, 0, true>(P, cc, c.w0, j0, j1);
+            else if (pass == PASS_WR) run_rows<PASS_W>(P, cc, j0, j1);
+            else if (pass == PASS_LR) run_rows<PASS_L>(P, cc, j0, j1);
             else run_pass<PASS_L, 0, true, true>(P, cc, c.smin, j0, j1);
             continue;
         }

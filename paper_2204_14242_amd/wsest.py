@@ -78,7 +78,8 @@ class wse_space(C.Structure):
 
 class wse_tuning(C.Structure):
     _fields_ = [("lds_slots", C.c_int32), ("table_slack_log2", C.c_int32),
-                ("item_evals", C.c_int64), ("groups_per_cu", C.c_int32), ("bitmap_log2", C.c_int32)]
+                ("item_evals", C.c_int64), ("groups_per_cu", C.c_int32), ("bitmap_log2", C.c_int32),
+                ("row_ranges", C.c_int32), ("pad", C.c_int32)]
 
 
 class wse_server_opts(C.Structure):
@@ -350,13 +351,13 @@ class Context:
         _check(lib().wse_get_tuning(self._ctx, C.byref(t)), self._ctx)
         return {"lds_slots": t.lds_slots, "table_slack_log2": t.table_slack_log2,
                 "item_evals": t.item_evals, "groups_per_cu": t.groups_per_cu,
-                "bitmap_log2": t.bitmap_log2}
+                "bitmap_log2": t.bitmap_log2, "row_ranges": t.row_ranges}
 
     def set_tuning(self, **kw):
         cur = self.tuning()
         cur.update(kw)
         t = wse_tuning(cur["lds_slots"], cur["table_slack_log2"], cur["item_evals"],
-                       cur["groups_per_cu"], cur["bitmap_log2"])
+                       cur["groups_per_cu"], cur["bitmap_log2"], cur["row_ranges"], 0)
         _check(lib().wse_set_tuning(self._ctx, C.byref(t)), self._ctx)
 
     def autotune(self, specs, sample=32):
@@ -366,7 +367,7 @@ class Context:
         _check(lib().wse_autotune(self._ctx, arr, len(specs), int(sample), C.byref(t)), self._ctx)
         return {"lds_slots": t.lds_slots, "table_slack_log2": t.table_slack_log2,
                 "item_evals": t.item_evals, "groups_per_cu": t.groups_per_cu,
-                "bitmap_log2": t.bitmap_log2}
+                "bitmap_log2": t.bitmap_log2, "row_ranges": t.row_ranges}
 
     def last_timings(self):
         t = (C.c_double * 8)()

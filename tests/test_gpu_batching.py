@@ -96,7 +96,8 @@ def test_results_do_not_depend_on_tuning(small_ctx):
     try:
         for t in [dict(lds_slots=1024, item_evals=1 << 12, groups_per_cu=1, bitmap_log2=0),
                   dict(lds_slots=4096, item_evals=1 << 22, table_slack_log2=3, groups_per_cu=32, bitmap_log2=8),
-                  dict(lds_slots=2048, item_evals=1 << 15, table_slack_log2=2, groups_per_cu=8, bitmap_log2=2)]:
+                  dict(lds_slots=2048, item_evals=1 << 15, table_slack_log2=2, groups_per_cu=8, bitmap_log2=2),
+                  dict(bitmap_log2=8, row_ranges=1)]:
             small_ctx.set_tuning(**t)
             got, grank = small_ctx.estimate(reg, mode=wsest.BATCHED)
             assert got.tobytes() == ref.tobytes(), t
@@ -129,3 +130,5 @@ def test_invalid_tuning_is_rejected(small_ctx):
         small_ctx.set_tuning(groups_per_cu=0)
     with pytest.raises(wsest.WseError):
         small_ctx.set_tuning(bitmap_log2=9)
+    with pytest.raises(wsest.WseError):
+        small_ctx.set_tuning(row_ranges=2)

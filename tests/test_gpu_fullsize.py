@@ -123,3 +123,25 @@ def test_stress_full_size(ctx, orc):
         res.append(r)
         ranks.append(rk)
     assert_same(got, np.concatenate(res), grank, np.concatenate(ranks), "stress full size")
+
+
+def test_row_ranges_equal_enumeration_full_size(ctx):
+    """Filling the wave and layer bitmaps from row ranges gives the same bytes
+    as evaluating every (thread, instruction) pair, at full sizes."""
+    from paper_2204_14242_amd import wsest
+    base = ctx.tuning()
+    for wl, n_gpu, seed in (("stencil_batched", 600, 31), ("lbm_batched", 160, 32)):
+        k, hw, sp = getattr(W, wl)()
+        kid, hid = ctx.register_kernel(k), ctx.register_hw(hw)
+        n = ctx.space_size(kid, hid, sp)
+        idx = sorted(random.Random(seed).sample(range(n), n_gpu))
+        spec = [(kid, hid, dict(sp, explicit=idx))]
+        say(f"case row ranges: {wl}, {len(idx)} configurations")
+        try:
+            ctx.set_tuning(row_ranges=0)
+            a, ra = ctx.estimate(spec, mode=wsest.BATCHED)
+            ctx.set_tuning(row_ranges=1)
+            b, rb = ctx.estimate(spec, mode=wsest.BATCHED)
+        finally:
+            ctx.set_tuning(**base)
+        assert a.tobytes() == b.tobytes() and np.array_equal(ra, rb), wl

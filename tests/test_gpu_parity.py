@@ -24,14 +24,16 @@ def say(msg):
 
 
 # every parity case runs with the sets kept as bitmaps wherever the key
-# ranges allow it, and again with hash tables only
-@pytest.fixture(scope="module", params=["bitmap", "hash"])
+# ranges allow it, again with hash tables only, and again with bitmaps
+# filled by row ranges where the kernel allows it
+@pytest.fixture(scope="module", params=["bitmap", "hash", "rows"])
 def ctx(request):
     if not gpu_available():
         pytest.skip("no GPU")
     from paper_2204_14242_amd import wsest
     c = wsest.Context(0, arena_bytes=8 << 30)
-    c.set_tuning(bitmap_log2=8 if request.param == "bitmap" else 0)
+    c.set_tuning(bitmap_log2=0 if request.param == "hash" else 8,
+                 row_ranges=1 if request.param == "rows" else 0)
     c.representation = request.param
     yield c
     c.close()
@@ -64,7 +66,7 @@ def test_stencil_64_sample(ctx, orc):
     # the representation asked for is the one that ran
     n_bitmap = ctx.last_stats()["bitmap_configs"]
     n_ok = int((got["status"] == 0).sum())
-    assert n_bitmap == (n_ok if ctx.representation == "bitmap" else 0)
+    assert n_bitmap == (0 if ctx.representation == "hash" else n_ok)
 
 
 def test_stencil_folding_and_elements(ctx, orc):
