@@ -40,9 +40,39 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--plain-sample", type=int, default=192,
                    help="configurations of the workload estimated in plain and batched form side by side")
+    p.add_argument("--no-row-ranges", dest="row_ranges", action="store_false",
+                   help="skip the leg that repeats the workload with per-row address ranges")
     p.add_argument("--serve-requests", type=int, default=24,
                    help="requests of the seeded Poisson trace replayed through the server (0 = skip)")
     return p.parse_args()
+
+
+def row_ranges_leg(ctx, specs, mode, out, rank, stream, n):
+    """The same workload with the wave and layer sets of lattice kernels filled
+    from per-row address ranges instead of per-thread evaluation; its result
+    bytes must equal those of the timed steps."""
+    import torch
+    ref = out.cpu().numpy().tobytes()
+    ref_rank = rank.cpu().numpy().tobytes()
+    base = ctx.tuning()
+    try:
+        ctx.set_tuning(row_ranges=1)
+        ctx.estimate(specs, mode=mode, out=out, rank=rank, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.estimate(specs, mode=mode, out=out, rank=rank, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        eval_ms = ctx.last_timings()[1]
+    finally:
+        ctx.set_tuning(**base)
+    same = out.cpu().numpy().tobytes() == ref and rank.cpu().numpy().tobytes() == ref_rank
+    if not same:
+        raise SystemExit("row-range results differ from per-thread evaluation")
+    print("row-range step done", file=sys.stderr, flush=True)
+    return {"configs_per_s": n / dt, "ms_per_step": dt * 1e3, "evaluation_ms": eval_ms, "identical": True,
+            "what": "wave and layer sets of lattice kernels on bitmaps filled from per-row address ranges "
+                    "(tuning row_ranges=1); block and warp-level store passes still evaluate every thread"}
 
 
 def plain_vs_batched(ctx, kid, hid, space, n, sample):
@@ -261,6 +291,8 @@ def main():
                      "evaluation_phase": {"achieved": phase, "frac": phase / VALU_PEAK_TOPS,
                                           "ms_per_step": eval_ms / a.steps}},
     }
+    if a.row_ranges:
+        line["row_ranges"] = row_ranges_leg(ctx, specs, mode, out, rank, stream, n)
     if a.plain_sample > 0:
         line["plain_vs_batched"] = plain_vs_batched(ctx, kid, hid, space, n, a.plain_sample)
     if a.serve_requests > 0:
