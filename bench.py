@@ -27,6 +27,32 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 OPS_PER_EVAL = 10
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_stencil_batched_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2204_14242_amd", "csrc", "wse_kernels.hip")
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain
+    copy), or None when that summary was taken on another workload or on a
+    kernel source other than the one built here."""
+    import hashlib
+    if workload != "stencil_batched" or not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    fields = {}
+    for ln in open(TRAFFIC_SUMMARY):
+        if ln.startswith("- ") and ": " in ln:
+            k, v = ln[2:].split(": ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel source sha256") != src:
+        return None
+    try:
+        return float(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -40,6 +66,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--plain-sample", type=int, default=192,
                    help="configurations of the workload estimated in plain and batched form side by side")
+    p.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                   help="copy this many GiB device to device once before the workload (a transfer of known "
+                        "size for scaling HBM byte counters)")
     p.add_argument("--no-row-ranges", dest="row_ranges", action="store_false",
                    help="skip the leg that repeats the workload with per-row address ranges")
     p.add_argument("--serve-requests", type=int, default=24,
@@ -231,6 +260,15 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     mode = wsest.BATCHED if a.mode == "batched" else wsest.PLAIN
     specs = [(kid, hid, space)]
+    if a.copy_calibration_gib > 0:
+        nbytes = int(a.copy_calibration_gib * (1 << 30))
+        src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copied {nbytes} bytes device to device", file=sys.stderr, flush=True)
+        del src, dst
     for i in range(a.warmup):
         ctx.estimate(specs, mode=mode, out=out, rank=rank, stream=stream)
         print(f"warmup {i} done", file=sys.stderr, flush=True)
@@ -285,7 +323,7 @@ def main():
                    "evaluations_per_step": st["evals"], "table_bytes_per_step": st["table_bytes"],
                    "eval_launches_per_step": st["eval_launches"], "arena_rounds": st["rounds"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(a.workload),
                      "kernel": kname, "avg_launch_ms": avg_ms, "lane_ops_per_launch": per_launch,
                      "ops_per_eval": OPS_PER_EVAL,
                      "evaluation_phase": {"achieved": phase, "frac": phase / VALU_PEAK_TOPS,
