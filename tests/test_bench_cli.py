@@ -1,0 +1,34 @@
+"""Host-side behaviour of bench.py that needs no GPU: the one-GPU rule and
+the traffic figure's guard on the kernel source."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    summary = tmp_path / "summary.md"
+    source = tmp_path / "kernels.hip"
+    source.write_bytes(b"__global__ void k() {}\n")
+    import hashlib
+    digest = hashlib.sha256(source.read_bytes()).hexdigest()
+    summary.write_text(f"- HBM bytes per launch: `1234.5`\n- kernel source sha256: `{digest}`\n")
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(summary))
+    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(source))
+    assert bench.measured_traffic("stencil_batched") == pytest.approx(1234.5)
+    assert bench.measured_traffic("stencil_plain") is None       # another workload
+    source.write_bytes(b"__global__ void k() { /* changed */ }\n")
+    assert bench.measured_traffic("stencil_batched") is None     # the kernel changed since
