@@ -201,7 +201,10 @@ wse_status wse_estimate(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces,
 /* Launch and table-sizing parameters of the evaluation kernels.  They
  * change speed only: every result is identical under every tuning. */
 typedef struct {
-    int32_t lds_slots;          /* slots of each of a workgroup's two LDS hash sets: 1024, 2048 or 4096 */
+    int32_t lds_slots;          /* slots of each of a workgroup's two LDS hash sets, and half the
+                                   entries of its bitmap word cache: 1024, 2048 or 4096 (the wave and
+                                   layer passes of lattice kernels on bitmaps keep a fixed cache of
+                                   2048 words) */
     int32_t table_slack_log2;   /* HBM hash tables hold at least 2^slack slots per key bound (1..3) */
     int64_t item_evals;         /* address evaluations per work item of a workgroup (2^12 .. 2^22) */
     int32_t groups_per_cu;      /* resident-loop workgroups per compute unit (1 .. 64) */

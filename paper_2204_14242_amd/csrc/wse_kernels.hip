@@ -266,7 +266,8 @@ struct RowOrder {
     int64_t units;
 };
 
-__device__ __forceinline__ RowOrder row_order(const Cfg& c, int64_t klo, int64_t khi)
+template <class C>
+__device__ __forceinline__ RowOrder row_order(const C& c, int64_t klo, int64_t khi)
 {
     RowOrder o;
     const int64_t nb0 = c.nb[0], b0 = c.b[0], T0 = c.T[0];
@@ -292,7 +293,8 @@ __device__ __forceinline__ RowOrder row_order(const Cfg& c, int64_t klo, int64_t
 
 // unit j of a row order: row of blocks r, thread row (ty, tz), first x of
 // the segment and end of the row's x range
-__device__ __forceinline__ void row_unit(const RowOrder& o, const Cfg& c, int64_t j, int64_t* r, int64_t* ty,
+template <class C>
+__device__ __forceinline__ void row_unit(const RowOrder& o, const C& c, int64_t j, int64_t* r, int64_t* ty,
                                          int64_t* tz, int64_t* x0, int64_t* xe)
 {
     int64_t loc, nseg, xa;
@@ -797,10 +799,20 @@ __device__ __forceinline__ int64_t group_cycles(bool valid, int64_t w, int log2g
     return wave_sum64(cyc);
 }
 
+// Read-only views of the configuration, kernel and hardware records, which
+// no kernel writes while it runs: in the constant address space, uniform
+// reads of them are scalar loads into scalar registers.
+typedef const __attribute__((address_space(4))) Cfg CfgR;
+typedef const __attribute__((address_space(4))) KernelDev KernelR;
+typedef const __attribute__((address_space(4))) HwDev HwR;
+typedef const __attribute__((address_space(4))) TableDesc TableR;
+
+__device__ __forceinline__ bool table_used(TableR& T) { return T.log2cap > 0 || T.words > 0; }
+
 struct PassCtx {
-    const Cfg* c;
-    const KernelDev* K;
-    const HwDev* H;
+    CfgR* c;
+    KernelR* K;
+    HwR* H;
     const ExprL* exl;
     const ExprA* exa;
     char* arena;
@@ -819,12 +831,15 @@ struct PassCtx {
     int wlog;                  // 2^wlog entries
 };
 
+// word cache entries of the lattice bitmap kernel (2^11 x 8 B = 16 KiB)
+constexpr int kLatticeCacheLog2 = 11;
+
 // Move every entry of a shared LDS set into the configuration's HBM table;
 // all threads of the workgroup take part.  The caller synchronises before
 // further inserts.
 __device__ void flush_set(PassCtx& P, unsigned long long* set, int q, int mode, bool probe_wsec)
 {
-    const TableDesc& T = P.c->tab[q];
+    TableR& T = P.c->tab[q];
     unsigned long long* slots = (unsigned long long*)(P.arena + T.off);
     bool overflow = false;
     for (int i = (int)threadIdx.x; i < P.lslots; i += (int)blockDim.x) {
@@ -838,7 +853,7 @@ __device__ void flush_set(PassCtx& P, unsigned long long* set, int q, int mode, 
             int tb = P.c->tag_bits;
             uint64_t key1 = e >> tb;
             unsigned tag = (unsigned)(e & (((uint64_t)1 << tb) - 1));
-            const TableDesc& W = P.c->tab[T_WSEC];
+            TableR& W = P.c->tab[T_WSEC];
             const unsigned long long* ws = (const unsigned long long*)(P.arena + W.off);
             int64_t pos = set_find(ws, W.log2cap, key1, W.pb);
             if (pos >= 0) {
@@ -914,10 +929,9 @@ struct IConst {
 };
 
 template <int KIND>
-__device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, const TableDesc& TS,
-                                              const TableDesc& TL)
+__device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, TableR& TS, TableR& TL)
 {
-    const Cfg& c = *P.c;
+    CfgR& c = *P.c;
     IConst r;
     int f;
     if (KIND == 0) {
@@ -1032,11 +1046,13 @@ __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base,
 }
 
 // word_probe for a step whose keys form runs: `base` is the same on every
-// lane, the active lanes (mask `am`) are one contiguous range and their keys
-// rise by 0 or 1 from lane to lane.  Then a run of equal words
-// holds every key between its ends, and its last lane forms the run's bits
-// from its own key and, in the first word, the first active lane's key,
-// with no scan.
+// lane, the lanes of mask `am` are one contiguous range and their keys rise
+// by 0 or 1 from lane to lane.  Then a run of equal words holds every key
+// between its ends, and its last lane forms the run's bits from its own key
+// and, in the first word, the key of the first lane of `am`, with no scan.
+// The active lanes are those of `am`, or fewer only where a key left its
+// table's range: then the item reports an error and its counts are void,
+// while every write still stays inside the configuration's tables.
 __device__ __forceinline__ WordProbe word_probe_runs(const PassCtx& P, uint32_t base, bool act, uint32_t key,
                                                      uint64_t am)
 {
@@ -1111,7 +1127,7 @@ __device__ __forceinline__ void set_key_range(PassCtx& P, uint32_t base, uint32_
 template <int PASS>
 __device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, int64_t j1)
 {
-    const Cfg& c = *P.c;
+    CfgR& c = *P.c;
     const int lane = lane_id();
     const int ls = P.H->log2_sector, ll = P.H->log2_line;
     const int64_t nb0 = c.nb[0], nb1 = c.nb[1];
@@ -1120,8 +1136,8 @@ __device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, 
     const int64_t T0 = c.T[0], T1 = c.T[1], T2 = c.T[2];
     const int64_t sy = c.sy, sz = c.sz, g = c.g, f1 = c.fold[1], f2 = c.fold[2];
     const int64_t uelem = c.uniform_elem;
-    const TableDesc& TS = c.tab[T_WSEC];
-    const TableDesc& TL = c.tab[PASS == PASS_L ? T_LLINE : T_WLINE];
+    TableR& TS = c.tab[T_WSEC];
+    TableR& TL = c.tab[PASS == PASS_L ? T_LLINE : T_WLINE];
     const bool do_sec = table_used(TS);
     const int64_t umin_s = TS.umin, span_s = TS.span, umin_l = TL.umin, span_l = TL.span;
     const uint32_t off_s = (uint32_t)((PASS == PASS_L ? TS.tag_off : TS.off) >> 2);
@@ -1210,7 +1226,7 @@ __device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, 
 template <int PASS, int KIND, bool DENSE, bool RUNS = false>
 __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, int64_t j1)
 {
-    const Cfg& c = *P.c;
+    CfgR& c = *P.c;
     const int lane = lane_id();
     // everything the loops read, loaded once into registers
     const int log2_warp = P.H->log2_warp, log2_group = P.H->log2_group, log2_bank = P.H->log2_bank;
@@ -1228,9 +1244,11 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     const int64_t smin = c.smin;
     const int tag_bits = c.tag_bits;
     int64_t acc_up_ld = 0, acc_up_st = 0, acc_cyc = 0, acc_lanes = 0, acc_warps = 0;
+    // a lane whose key left its table's range (reported once, after the item)
+    bool out_of_range = false;
     constexpr bool ROW = PASS == PASS_W || PASS == PASS_L;  // row order
-    const TableDesc& TS = c.tab[PASS == PASS_B ? T_BSEC : T_WSEC];
-    const TableDesc& TL = c.tab[PASS == PASS_L ? T_LLINE : (PASS == PASS_B ? T_BLINE : T_WLINE)];
+    TableR& TS = c.tab[PASS == PASS_B ? T_BSEC : T_WSEC];
+    TableR& TL = c.tab[PASS == PASS_L ? T_LLINE : (PASS == PASS_B ? T_BLINE : T_WLINE)];
     const int sec_pb = PASS == PASS_W ? 2 : (PASS == PASS_L ? tag_bits : 0);
     const int line_pb = PASS == PASS_L ? tag_bits : 0;
     const int sec_mode = PASS == PASS_W ? MODE_OR : (PASS == PASS_L ? MODE_MAX : MODE_SET);
@@ -1377,7 +1395,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         acc_cyc += group_cycles(valid, addr >> log2_bank, log2_group, n_banks, pair_words);
                         if (!st) {
                             bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
-                            if (__ballot(valid && !ok)) P.err |= 1;
+                            out_of_range |= valid && !ok;
                             bool act = valid && ok;
                             if (DENSE) {
                                 WordProbe a = word_probe(P, bs, act, (uint32_t)(us + readlane64(ic.fs, q) - 1));
@@ -1396,16 +1414,17 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         if (st) acc_up_st += warp_distinct(valid, sec, log2_warp);
                     } else if (PASS == PASS_W) {
                         bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
-                        if (__ballot(valid && !ok)) P.err |= 1;
+                        out_of_range |= valid && !ok;
                         bool act = valid && ok;
                         if (DENSE) {
                             const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
                             const uint32_t kl = (uint32_t)(ul + readlane64(ic.fl, q) - 1);
                             WordProbe a, b;
                             if (FAST) {
-                                const uint64_t am = __ballot(act);
-                                a = word_probe_runs(P, bs + (st ? words_s : 0u), act, ks, am);
-                                b = word_probe_runs(P, bl, act, kl, am);
+                                // every valid key is in range unless the item
+                                // reports an error: the valid lanes give the range
+                                a = word_probe_runs(P, bs + (st ? words_s : 0u), act, ks, vmask);
+                                b = word_probe_runs(P, bl, act, kl, vmask);
                             } else {
                                 a = word_probe(P, bs + (st ? words_s : 0u), act, ks);
                                 b = word_probe(P, bl, act, kl);
@@ -1422,7 +1441,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         }
                     } else {
                         bool ok = (uint64_t)ul < (uint64_t)span_l;
-                        if (__ballot(valid && !ok)) P.err |= 1;
+                        out_of_range |= valid && !ok;
                         if (DENSE) {
                             const bool actl = valid && ok;
                             const bool in = do_sec && valid && (uint64_t)us < (uint64_t)span_s;
@@ -1430,8 +1449,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                             const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
                             WordProbe a = {0ull, 0u, 0u, 0u}, b;
                             if (FAST) {
-                                const uint64_t aml = __ballot(actl), ams = __ballot(in);
-                                b = word_probe_runs(P, bl, actl, kl, aml);
+                                const uint64_t ams = __ballot(in);
+                                b = word_probe_runs(P, bl, actl, kl, vmask);
                                 if (ams) a = word_probe_runs(P, bs, in, ks, ams);
                             } else {
                                 b = word_probe(P, bl, actl, kl);
@@ -1465,6 +1484,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             }
         }
     }
+    if (__ballot(out_of_range)) P.err |= 1;
     if (DENSE) {
         // final flush of the workgroup's cached words
         __syncthreads();
@@ -1507,10 +1527,12 @@ __device__ __forceinline__ const void* readfirstlane_ptr(const void* p)
 // the four waves of a workgroup share the LDS (two hash sets of lds_slots
 // entries, or a cache of 2 * lds_slots bitmap words) and cooperate on one
 // item at a time.  LATTICE_BITMAP instantiates only the wave and layer
-// passes of lattice kernels on bitmaps, the bulk of the work, which then run
-// with fewer registers and more waves per SIMD.
+// passes of lattice kernels on bitmaps, the bulk of the work.  That
+// instance keeps a fixed cache of 2^kLatticeCacheLog2 words (16 KiB) and is
+// built for seven waves per SIMD (seven workgroups per CU): its steps wait
+// on LDS round trips, and more waves hide them.
 template <bool LATTICE_BITMAP>
-__global__ __launch_bounds__(256, LATTICE_BITMAP ? 4 : 1) void k_eval(const WorkEntry* __restrict__ work_all,
+__global__ __launch_bounds__(256, LATTICE_BITMAP ? 7 : 1) void k_eval(const WorkEntry* __restrict__ work_all,
                                               const RoundDesc* __restrict__ rd, int which, DevTables t,
                                               int lds_slots)
 {
@@ -1520,14 +1542,15 @@ __global__ __launch_bounds__(256, LATTICE_BITMAP ? 4 : 1) void k_eval(const Work
     const int64_t n_items = rd->items[which];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int llog = 31 - __clz(lds_slots);
+    const int wlog = LATTICE_BITMAP ? kLatticeCacheLog2 : llog + 1;
     unsigned long long* set0 = lds;
     unsigned long long* set1 = lds + lds_slots;
     uint32_t* cnt = (uint32_t*)(lds + 2 * (size_t)lds_slots);
-    for (int i = (int)threadIdx.x; i < 2 * lds_slots; i += (int)blockDim.x) lds[i] = 0;
+    for (int i = (int)threadIdx.x; i < (1 << wlog); i += (int)blockDim.x) lds[i] = 0;
     __syncthreads();
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const WorkEntry* W = find_entry(work, n_work, item);
-        const Cfg& c = *(const Cfg*)readfirstlane_ptr(W->cfg);
+        CfgR& c = *(CfgR*)readfirstlane_ptr(W->cfg);
         Counters* cc = (Counters*)readfirstlane_ptr(W->ctr);
         char* tables = (char*)readfirstlane_ptr(W->tables);
         const int64_t local = item - W->item_start;
@@ -1537,8 +1560,8 @@ __global__ __launch_bounds__(256, LATTICE_BITMAP ? 4 : 1) void k_eval(const Work
 
         PassCtx P;
         P.c = &c;
-        P.K = &t.kernels[c.kernel_id];
-        P.H = &t.hws[c.hw_id];
+        P.K = (KernelR*)&t.kernels[c.kernel_id];
+        P.H = (HwR*)&t.hws[c.hw_id];
         P.exl = c.kind == 0 ? t.expansions[c.expansion_id].ex : nullptr;
         P.exa = c.kind == 1 ? (const ExprA*)P.K->items : nullptr;
         P.arena = tables;
@@ -1552,7 +1575,7 @@ __global__ __launch_bounds__(256, LATTICE_BITMAP ? 4 : 1) void k_eval(const Work
         P.step = 0;
         P.err = 0;
         P.wtab = lds;
-        P.wlog = llog + 1;
+        P.wlog = wlog;
         if (LATTICE_BITMAP) {
             if (pass == PASS_W) run_pass<PASS_W, 0, true, true>(P, cc, c.w0, j0, j1);
             else if (pass == PASS_WS) run_pass<PASS_WS, 0, true>(P, cc, c.w0, j0, j1);
@@ -1601,9 +1624,11 @@ size_t eval_lds_bytes(int lds_slots)
 hipError_t launch_eval(const WorkEntry* work, const RoundDesc* rd, int which, DevTables t, int lds_slots,
                        int64_t groups, hipStream_t s)
 {
+    // the lattice bitmap kernel holds its word cache only
     if (which == LIST_EVAL_DL)
         hipLaunchKernelGGL(k_eval<true>, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup),
-                           eval_lds_bytes(lds_slots), s, work, rd, which, t, lds_slots);
+                           ((size_t)1 << kLatticeCacheLog2) * sizeof(unsigned long long), s, work, rd, which, t,
+                           lds_slots);
     else
         hipLaunchKernelGGL(k_eval<false>, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup),
                            eval_lds_bytes(lds_slots), s, work, rd, which, t, lds_slots);
@@ -1623,10 +1648,10 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
     const int64_t n_waves = (int64_t)gridDim.x * kWavesPerGroup;
     for (int64_t item = (int64_t)blockIdx.x * kWavesPerGroup + wave; item < n_items; item += n_waves) {
     const WorkEntry* W = find_entry(work, n_work, item);
-    const Cfg& c = *(const Cfg*)readfirstlane_ptr(W->cfg);
+    CfgR& c = *(CfgR*)readfirstlane_ptr(W->cfg);
     const char* arena = (const char*)readfirstlane_ptr(W->tables);
     int q = W->what;
-    const TableDesc& T = c.tab[q];
+    TableR& T = c.tab[q];
     const unsigned long long* slots = (const unsigned long long*)(arena + T.off);
     int64_t local = item - W->item_start;
     int64_t i0 = local * W->per_item;
