@@ -978,6 +978,13 @@ __device__ __forceinline__ void flush_words(PassCtx& P)
     }
 }
 
+// Cache slot of a bitmap word (offset + 1): a multiplicative hash of its low
+// 24 bits, on the full-rate 24-bit multiplier.
+__device__ __forceinline__ uint32_t word_slot(uint32_t w1, int wlog)
+{
+    return ((w1 & 0xffffffu) * 0x9e3779u) >> (32 - wlog);
+}
+
 // One lane's pending update of a bitmap word: the merged bits it writes, the
 // word's cache slot and the slot's content when read.
 struct WordProbe {
@@ -1040,7 +1047,7 @@ __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base,
     WordProbe r;
     r.k1 = lead ? w1 : 0u;
     r.bits = bits;
-    r.slot = (w1 * 0x9e3779b1u) >> (32 - P.wlog);
+    r.slot = word_slot(w1, P.wlog);
     r.old = P.wtab[r.slot];
     return r;
 }
@@ -1066,7 +1073,7 @@ __device__ __forceinline__ WordProbe word_probe_runs(const PassCtx& P, uint32_t 
     WordProbe r;
     r.k1 = lead ? w1 : 0u;
     r.bits = (0xffffffffu >> (31 - (key & 31))) & (0xffffffffu << lo);
-    r.slot = (w1 * 0x9e3779b1u) >> (32 - P.wlog);
+    r.slot = word_slot(w1, P.wlog);
     r.old = P.wtab[r.slot];
     return r;
 }
@@ -1083,19 +1090,19 @@ __device__ __forceinline__ void word_commit(PassCtx& P, WordProbe r)
 {
     if (r.k1 == 0) return;
     unsigned long long old = r.old;
-    for (;;) {
-        const bool mine = (uint32_t)(old >> 32) == r.k1;
-        const unsigned long long want =
-            mine ? (old | r.bits) : (((unsigned long long)r.k1 << 32) | r.bits);
-        if (want == old) break;
-        const unsigned long long prev = atomicCAS(&P.wtab[r.slot], old, want);
-        if (prev == old) {
-            if (!mine && old != 0)
-                atomicOr(&((unsigned*)P.arena)[(uint32_t)(old >> 32) - 1], (uint32_t)old);
-            break;
-        }
+    bool mine = (uint32_t)(old >> 32) == r.k1;
+    unsigned long long want = mine ? (old | r.bits) : (((unsigned long long)r.k1 << 32) | r.bits);
+    if (want == old) return;
+    unsigned long long prev = atomicCAS(&P.wtab[r.slot], old, want);
+    // another lane or wave changed the slot first: start again from its content
+    while (prev != old) {
         old = prev;
+        mine = (uint32_t)(old >> 32) == r.k1;
+        want = mine ? (old | r.bits) : (((unsigned long long)r.k1 << 32) | r.bits);
+        if (want == old) return;
+        prev = atomicCAS(&P.wtab[r.slot], old, want);
     }
+    if (!mine && old != 0) atomicOr(&((unsigned*)P.arena)[(uint32_t)(old >> 32) - 1], (uint32_t)old);
 }
 
 // Set the bits [k_lo, k_hi] (inclusive, k_lo <= k_hi) of the bitmap at word
@@ -1109,7 +1116,7 @@ __device__ __forceinline__ void set_key_range(PassCtx& P, uint32_t base, uint32_
         WordProbe r;
         r.k1 = base + w + 1;
         r.bits = (0xffffffffu >> (31 - hi)) & (0xffffffffu << lo);
-        r.slot = (r.k1 * 0x9e3779b1u) >> (32 - P.wlog);
+        r.slot = word_slot(r.k1, P.wlog);
         r.old = P.wtab[r.slot];
         word_commit(P, r);
     }
