@@ -989,9 +989,10 @@ __device__ __forceinline__ uint32_t word_slot(uint32_t w1, int wlog)
 // word's cache slot and the slot's content when read.
 struct WordProbe {
     unsigned long long old;
-    uint32_t k1;      // word offset + 1; 0 = this lane has nothing to write
+    uint32_t k1;      // word offset + 1
     uint32_t bits;
     uint32_t slot;
+    bool lead;        // this lane writes the word
 };
 
 // How far lanes merge their bits before writing: 2 = within aligned groups
@@ -1045,7 +1046,8 @@ __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base,
         lead = act && (nw1 != w1 || (lane_id() & (group - 1)) == group - 1);
     }
     WordProbe r;
-    r.k1 = lead ? w1 : 0u;
+    r.k1 = w1;
+    r.lead = lead;
     r.bits = bits;
     r.slot = word_slot(w1, P.wlog);
     r.old = P.wtab[r.slot];
@@ -1071,7 +1073,8 @@ __device__ __forceinline__ WordProbe word_probe_runs(const PassCtx& P, uint32_t 
     const bool lead = act && nw1 != w1;
     const uint32_t lo = w1 == wfirst1 ? (kfirst & 31) : 0u;
     WordProbe r;
-    r.k1 = lead ? w1 : 0u;
+    r.k1 = w1;
+    r.lead = lead;
     r.bits = (0xffffffffu >> (31 - (key & 31))) & (0xffffffffu << lo);
     r.slot = word_slot(w1, P.wlog);
     r.old = P.wtab[r.slot];
@@ -1088,7 +1091,7 @@ __device__ __forceinline__ void probes_issued() { asm volatile("" ::: "memory");
 // meet in one slot serialise correctly.
 __device__ __forceinline__ void word_commit(PassCtx& P, WordProbe r)
 {
-    if (r.k1 == 0) return;
+    if (!r.lead) return;
     unsigned long long old = r.old;
     bool mine = (uint32_t)(old >> 32) == r.k1;
     unsigned long long want = mine ? (old | r.bits) : (((unsigned long long)r.k1 << 32) | r.bits);
@@ -1115,6 +1118,7 @@ __device__ __forceinline__ void set_key_range(PassCtx& P, uint32_t base, uint32_
         const uint32_t hi = w == w_hi ? (k_hi & 31) : 31u;
         WordProbe r;
         r.k1 = base + w + 1;
+        r.lead = true;
         r.bits = (0xffffffffu >> (31 - hi)) & (0xffffffffu << lo);
         r.slot = word_slot(r.k1, P.wlog);
         r.old = P.wtab[r.slot];
@@ -1454,7 +1458,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                             const bool in = do_sec && valid && (uint64_t)us < (uint64_t)span_s;
                             const uint32_t kl = (uint32_t)(ul + readlane64(ic.fl, q) - 1);
                             const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
-                            WordProbe a = {0ull, 0u, 0u, 0u}, b;
+                            WordProbe a = {0ull, 0u, 0u, 0u, false}, b;
                             if (FAST) {
                                 const uint64_t ams = __ballot(in);
                                 b = word_probe_runs(P, bl, actl, kl, vmask);
@@ -1553,7 +1557,13 @@ __global__ __launch_bounds__(256, LATTICE_BITMAP ? 7 : 1) void k_eval(const Work
     unsigned long long* set0 = lds;
     unsigned long long* set1 = lds + lds_slots;
     uint32_t* cnt = (uint32_t*)(lds + 2 * (size_t)lds_slots);
-    for (int i = (int)threadIdx.x; i < (1 << wlog); i += (int)blockDim.x) lds[i] = 0;
+    unsigned long long* wtab = lds;
+    if constexpr (LATTICE_BITMAP) {
+        // a fixed cache at a fixed LDS address
+        __shared__ unsigned long long lattice_cache[1 << kLatticeCacheLog2];
+        wtab = lattice_cache;
+    }
+    for (int i = (int)threadIdx.x; i < (1 << wlog); i += (int)blockDim.x) wtab[i] = 0;
     __syncthreads();
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const WorkEntry* W = find_entry(work, n_work, item);
@@ -1581,7 +1591,7 @@ __global__ __launch_bounds__(256, LATTICE_BITMAP ? 7 : 1) void k_eval(const Work
         P.fill0 = P.fill1 = 0;
         P.step = 0;
         P.err = 0;
-        P.wtab = lds;
+        P.wtab = wtab;
         P.wlog = wlog;
         if (LATTICE_BITMAP) {
             if (pass == PASS_W) run_pass<PASS_W, 0, true, true>(P, cc, c.w0, j0, j1);
@@ -1631,11 +1641,10 @@ size_t eval_lds_bytes(int lds_slots)
 hipError_t launch_eval(const WorkEntry* work, const RoundDesc* rd, int which, DevTables t, int lds_slots,
                        int64_t groups, hipStream_t s)
 {
-    // the lattice bitmap kernel holds its word cache only
+    // the lattice bitmap kernel holds its word cache only, statically
     if (which == LIST_EVAL_DL)
-        hipLaunchKernelGGL(k_eval<true>, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup),
-                           ((size_t)1 << kLatticeCacheLog2) * sizeof(unsigned long long), s, work, rd, which, t,
-                           lds_slots);
+        hipLaunchKernelGGL(k_eval<true>, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup), 0, s, work, rd,
+                           which, t, lds_slots);
     else
         hipLaunchKernelGGL(k_eval<false>, dim3((unsigned)groups), dim3(kLanes * kWavesPerGroup),
                            eval_lds_bytes(lds_slots), s, work, rd, which, t, lds_slots);
