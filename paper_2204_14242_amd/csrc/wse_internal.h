@@ -121,6 +121,8 @@ struct Cfg {
     int64_t l_units;            // layer pass: segments of its blocks' threads in row order
     int64_t w_units;            // wave pass: segments of its blocks' threads in row order
     int64_t w_rows, l_rows;     // thread rows of the wave and layer passes' blocks
+    int64_t s_lo, s_hi;         // lattice kernels of one element size: smallest and largest
+                                // instruction byte offset (align + elem * c0); s_lo > s_hi if unknown
     TableDesc tab[N_TABLES];
     int64_t table_bytes;        // arena bytes this configuration needs
 };

@@ -486,6 +486,26 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         c.E = X.E;
         c.n_ld = X.n_ld;
         c.uniform_elem = c.elem ? c.elem : K.uniform_elem;
+        // offsets of the expanded instructions, for the evaluation's
+        // per-segment range proofs
+        c.s_lo = 1;
+        c.s_hi = 0;
+        if (c.uniform_elem > 0) {
+            __int128 lo = 0, hi = 0;
+            for (int e = 0; e < c.E; e++) {
+                const ExprL& x = X.ex[e];
+                const __int128 S = (__int128)K.align[x.f] +
+                                   (__int128)c.uniform_elem * ((__int128)x.v[0] + (__int128)c.sy * x.v[1] +
+                                                               (__int128)c.sz * x.v[2]);
+                if (e == 0 || S < lo) lo = S;
+                if (e == 0 || S > hi) hi = S;
+            }
+            const __int128 LIM = (__int128)1 << 62;
+            if (c.E > 0 && lo > -LIM && hi < LIM) {
+                c.s_lo = (int64_t)lo;
+                c.s_hi = (int64_t)hi;
+            }
+        }
     } else {
         if (c.outer[0] <= 0 || c.outer[1] <= 0 || c.outer[2] <= 0) {
             c.status = -1;
@@ -1296,11 +1316,13 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             const bool seg_ok = jg + P.wave < j1;
             if (DENSE && !seg_ok) break;
             int64_t tx, ty, tz, gx, gy, gz, kcur, bcur[3];
+            int64_t seg_x0 = 0;
             bool valid;
             if (ROW) {
                 // row order: 64 consecutive x of one thread row
                 int64_t r, x0, xe;
                 row_unit(ro, c, seg_ok ? jg + P.wave : 0, &r, &ty, &tz, &x0, &xe);
+                seg_x0 = x0;
                 bcur[1] = r % nb1;
                 bcur[2] = r / nb1;
                 gx = x0 + lane;
@@ -1376,8 +1398,14 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             if (RUNS && DENSE && PASS == PASS_L)
                 seg_runs = seg_runs &&
                            __ballot(valid && band != (uint32_t)__builtin_amdgcn_readfirstlane((int)band)) == 0;
-            auto instructions = [&](auto runs_tag) {
-            constexpr bool FAST = decltype(runs_tag)::value;
+            // Instruction loop variants: 0 = general; run-end probes with
+            // 1 = range checks per lane, 2 = every key of the segment in its
+            // table's range (no checks), 3 = layer pass with every line key in
+            // range and no sector in the wave's sector range.
+            auto instructions = [&](auto mode_tag) {
+            constexpr int MODE = decltype(mode_tag)::value;
+            constexpr bool FAST = MODE >= 1;
+            constexpr bool CHECK = MODE <= 1;
             for (int q = 0; q < n_in; q++) {
                 int new0 = 0, new1 = 0;
                 if (vmask) {
@@ -1424,8 +1452,11 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                     } else if (PASS == PASS_WS) {
                         if (st) acc_up_st += warp_distinct(valid, sec, log2_warp);
                     } else if (PASS == PASS_W) {
-                        bool ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
-                        out_of_range |= valid && !ok;
+                        bool ok = true;
+                        if (CHECK) {
+                            ok = (uint64_t)us < (uint64_t)span_s && (uint64_t)ul < (uint64_t)span_l;
+                            out_of_range |= valid && !ok;
+                        }
                         bool act = valid && ok;
                         if (DENSE) {
                             const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
@@ -1451,18 +1482,25 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                             new1 = lds_add(P, P.set1, kl, line_pb, line_mode);
                         }
                     } else {
-                        bool ok = (uint64_t)ul < (uint64_t)span_l;
-                        out_of_range |= valid && !ok;
+                        bool ok = true;
+                        if (CHECK) {
+                            ok = (uint64_t)ul < (uint64_t)span_l;
+                            out_of_range |= valid && !ok;
+                        }
                         if (DENSE) {
                             const bool actl = valid && ok;
-                            const bool in = do_sec && valid && (uint64_t)us < (uint64_t)span_s;
+                            const bool in = do_sec && valid && (MODE == 2 || (uint64_t)us < (uint64_t)span_s);
                             const uint32_t kl = (uint32_t)(ul + readlane64(ic.fl, q) - 1);
                             const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
                             WordProbe a = {0ull, 0u, 0u, 0u, false}, b;
                             if (FAST) {
-                                const uint64_t ams = __ballot(in);
                                 b = word_probe_runs(P, bl, actl, kl, vmask);
-                                if (ams) a = word_probe_runs(P, bs, in, ks, ams);
+                                if (MODE == 1) {
+                                    const uint64_t ams = __ballot(in);
+                                    if (ams) a = word_probe_runs(P, bs, in, ks, ams);
+                                } else if (MODE == 2) {
+                                    a = word_probe_runs(P, bs, in, ks, vmask);
+                                }
                             } else {
                                 b = word_probe(P, bl, actl, kl);
                                 if (do_sec) a = word_probe(P, bs, in, ks);
@@ -1487,11 +1525,37 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 if (!DENSE) step_sync<PASS>(P, new0, new1, do_sec);
             }
             };
+            using General = std::integral_constant<int, 0>;
             if constexpr (RUNS) {
-                if (seg_runs) instructions(std::true_type{});
-                else instructions(std::false_type{});
+                if (seg_runs) {
+                    // the segment's address range over all instructions:
+                    // lane 0 at the smallest offset, the last valid lane at
+                    // the largest (no proof when the offsets are unknown)
+                    const int64_t s_lo = c.s_lo, s_hi = c.s_hi;
+                    const int64_t a_lo = (seg_x0 + g + sy * (f1 * gy + g) + sz * (f2 * gz + g)) * uelem + s_lo;
+                    const int64_t a_hi = a_lo - s_lo + (int64_t)(__popcll(vmask) - 1) * uelem + s_hi;
+                    const bool known = s_lo <= s_hi;
+                    const bool lines_in = known && (a_lo >> ll) >= umin_l && (a_hi >> ll) < umin_l + span_l;
+                    const bool secs_in =
+                        known && do_sec && (a_lo >> ls) >= umin_s && (a_hi >> ls) < umin_s + span_s;
+                    const bool secs_out =
+                        !do_sec || (known && ((a_hi >> ls) < umin_s || (a_lo >> ls) >= umin_s + span_s));
+                    // (keys out of range mean a broken layout: the checked
+                    // general loop reports them)
+                    if (lines_in && secs_in) {
+                        instructions(std::integral_constant<int, 2>{});
+                    } else if constexpr (PASS == PASS_L) {
+                        if (lines_in && secs_out) instructions(std::integral_constant<int, 3>{});
+                        else if (lines_in) instructions(std::integral_constant<int, 1>{});
+                        else instructions(General{});
+                    } else {
+                        instructions(General{});
+                    }
+                } else {
+                    instructions(General{});
+                }
             } else {
-                instructions(std::false_type{});
+                instructions(General{});
             }
         }
     }
