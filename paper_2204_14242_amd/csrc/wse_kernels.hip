@@ -946,6 +946,9 @@ struct IConst {
     int64_t fs, fl;  // field * span + 1 of the pass's sector and line tables
     int32_t st, elem;
     int64_t kt[3], kb[3];  // affine: index coefficients of tid and bid
+    // S + (fl - 1 - line umin) * line bytes, modulo 2^64: the low 32 bits of
+    // (address - S + SL) >> log2(line) are the line key itself
+    uint64_t SL;
 };
 
 template <int KIND>
@@ -978,6 +981,7 @@ __device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, TableR& T
     }
     r.fs = (int64_t)f * TS.span + 1;
     r.fl = (int64_t)f * TL.span + 1;
+    r.SL = (uint64_t)r.S + (((uint64_t)r.fl - 1u - (uint64_t)TL.umin) << P.H->log2_line);
     return r;
 }
 
@@ -1075,18 +1079,13 @@ __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base,
 }
 
 // word_probe for a step whose keys form runs: `base` is the same on every
-// lane, the lanes of mask `am` are one contiguous range and their keys rise
-// by 0 or 1 from lane to lane.  Then a run of equal words holds every key
-// between its ends, and its last lane forms the run's bits from its own key
-// and, in the first word, the key of the first lane of `am`, with no scan.
-// The active lanes are those of `am`, or fewer only where a key left its
-// table's range: then the item reports an error and its counts are void,
-// while every write still stays inside the configuration's tables.
-__device__ __forceinline__ WordProbe word_probe_runs(const PassCtx& P, uint32_t base, bool act, uint32_t key,
-                                                     uint64_t am)
+// lane, the active lanes are one contiguous range and their keys rise by 0
+// or 1 from lane to lane, from `kfirst` on.  Then a run of equal words holds
+// every key between its ends, and its last lane forms the run's bits from
+// its own key and, in the first word, `kfirst`, with no scan.
+__device__ __forceinline__ WordProbe word_probe_seg(const PassCtx& P, uint32_t base, bool act, uint32_t key,
+                                                    uint32_t kfirst)
 {
-    const int first = am ? __builtin_ctzll(am) : 0;
-    const uint32_t kfirst = (uint32_t)__builtin_amdgcn_readlane((int)key, first);
     const uint32_t w1 = act ? base + (key >> 5) + 1 : 0xffffffffu;
     const uint32_t wfirst1 = base + (kfirst >> 5) + 1;
     const uint32_t nw1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x130, 0xf, 0xf, true);  // wave_shl:1
@@ -1099,6 +1098,18 @@ __device__ __forceinline__ WordProbe word_probe_runs(const PassCtx& P, uint32_t 
     r.slot = word_slot(w1, P.wlog);
     r.old = P.wtab[r.slot];
     return r;
+}
+
+// word_probe_seg whose first key is that of the first lane of mask `am`
+// (the lanes of `am` are one contiguous range).  The active lanes are those
+// of `am`, or fewer only where a key left its table's range: then the item
+// reports an error and its counts are void, while every write still stays
+// inside the configuration's tables.
+__device__ __forceinline__ WordProbe word_probe_runs(const PassCtx& P, uint32_t base, bool act, uint32_t key,
+                                                     uint64_t am)
+{
+    const int first = am ? __builtin_ctzll(am) : 0;
+    return word_probe_seg(P, base, act, key, (uint32_t)__builtin_amdgcn_readlane((int)key, first));
 }
 
 // Keeps the compiler from sinking the probes' slot reads into their commits,
@@ -1184,7 +1195,7 @@ __device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, 
         const bool mine = e0 + lane < E;
         IConst ic;
         if (mine) ic = load_iconst<0>(P, e0 + lane, TS, TL);
-        else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}};
+        else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}, 0};
         for (int64_t u = j0 + P.wave; u < j1; u += kWavesPerGroup) {
             const int64_t r = ro.r0 + u / rows_per;
             const int64_t tr = u % rows_per;
@@ -1303,7 +1314,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
         const int n_in = E - e0 < kLanes ? E - e0 : kLanes;
         IConst ic;
         if (e0 + lane < E) ic = load_iconst<KIND>(P, e0 + lane, TS, TL);
-        else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}};
+        else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}, 0};
         const int32_t meta = ic.st | (ic.elem << 1);
 
         // the waves interleave segments (hash configurations in lockstep)
@@ -1387,6 +1398,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             int64_t base = 0;
             if (KIND == 0) base = (gx + g) + sy * (f1 * gy + g) + sz * (f2 * gz + g);
             const int64_t ubase = uelem ? base * uelem : 0;
+            // row order: lane 0's point is the segment's first x
+            const int64_t ubase0 = (seg_x0 + g + sy * (f1 * gy + g) + sz * (f2 * gz + g)) * uelem;
             // Lattice kernels in row order with one element size: the lanes are
             // consecutive x of one thread row, so addresses rise by the element
             // size from lane to lane, and while the element fits a sector the
@@ -1398,14 +1411,15 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             if (RUNS && DENSE && PASS == PASS_L)
                 seg_runs = seg_runs &&
                            __ballot(valid && band != (uint32_t)__builtin_amdgcn_readfirstlane((int)band)) == 0;
-            // Instruction loop variants: 0 = general; run-end probes with
-            // 1 = range checks per lane, 2 = every key of the segment in its
-            // table's range (no checks), 3 = layer pass with every line key in
-            // range and no sector in the wave's sector range.
+            // Instruction loop variants: 0 = general, with range checks per
+            // lane; run-end probes with every line key of the segment in its
+            // table's range and 1 = layer sectors checked per lane, 2 = every
+            // sector key in range too, 3 = (layer pass) no sector in the
+            // wave's sector range.
             auto instructions = [&](auto mode_tag) {
             constexpr int MODE = decltype(mode_tag)::value;
             constexpr bool FAST = MODE >= 1;
-            constexpr bool CHECK = MODE <= 1;
+            constexpr bool CHECK = MODE == 0;
             for (int q = 0; q < n_in; q++) {
                 int new0 = 0, new1 = 0;
                 if (vmask) {
@@ -1490,11 +1504,23 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         if (DENSE) {
                             const bool actl = valid && ok;
                             const bool in = do_sec && valid && (MODE == 2 || (uint64_t)us < (uint64_t)span_s);
-                            const uint32_t kl = (uint32_t)(ul + readlane64(ic.fl, q) - 1);
+                            // (every line key in range: the key straight from the
+                            // address, shifted with the table offsets folded in)
+                            const uint32_t kl =
+                                MODE == 3 ? (uint32_t)(((uint64_t)ubase + (uint64_t)readlane64((int64_t)ic.SL, q)) >> ll)
+                                          : (uint32_t)(ul + readlane64(ic.fl, q) - 1);
                             const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
                             WordProbe a = {0ull, 0u, 0u, 0u, false}, b;
                             if (FAST) {
-                                b = word_probe_runs(P, bl, actl, kl, vmask);
+                                if (MODE == 3) {
+                                    // lane 0's key, from scalar registers
+                                    const uint32_t kfirst = (uint32_t)(((uint64_t)ubase0 +
+                                                                        (uint64_t)readlane64((int64_t)ic.SL, q)) >>
+                                                                       ll);
+                                    b = word_probe_seg(P, bl, actl, kl, kfirst);
+                                } else {
+                                    b = word_probe_runs(P, bl, actl, kl, vmask);
+                                }
                                 if (MODE == 1) {
                                     const uint64_t ams = __ballot(in);
                                     if (ams) a = word_probe_runs(P, bs, in, ks, ams);
@@ -1532,7 +1558,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                     // lane 0 at the smallest offset, the last valid lane at
                     // the largest (no proof when the offsets are unknown)
                     const int64_t s_lo = c.s_lo, s_hi = c.s_hi;
-                    const int64_t a_lo = (seg_x0 + g + sy * (f1 * gy + g) + sz * (f2 * gz + g)) * uelem + s_lo;
+                    const int64_t a_lo = ubase0 + s_lo;
                     const int64_t a_hi = a_lo - s_lo + (int64_t)(__popcll(vmask) - 1) * uelem + s_hi;
                     const bool known = s_lo <= s_hi;
                     const bool lines_in = known && (a_lo >> ll) >= umin_l && (a_hi >> ll) < umin_l + span_l;
