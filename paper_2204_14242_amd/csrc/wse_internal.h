@@ -114,7 +114,8 @@ struct Cfg {
     int64_t s[3];
     int32_t order[3], n_order;  // non-empty layer sets by recency
     int32_t dense;              // bitmaps instead of hash tables: bit 0 the block pass's
-                                // tables, bit 1 the wave and layer passes'
+                                // tables, bit 1 the wave and layer passes'; bit 2: the wave's
+                                // lines are counted from its sector bitmaps (no line table)
     int32_t pad2;
     int64_t sy, sz, g;
     int64_t evals[3];           // thread x instruction evaluations per pass (upper bound)

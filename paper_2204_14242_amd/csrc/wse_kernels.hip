@@ -623,6 +623,27 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         // the evaluations that can reach it
         if ((keys >> bitmap_log2) > (uint64_t)ev[q] || keys >= ((uint64_t)1 << 32)) dense_g[q >= T_WSEC] = false;
     }
+    // Wave sets on bitmaps: a line is touched when any of its sectors is, so
+    // the wave's line set follows from its sector bitmaps if these start and
+    // end on line boundaries.  The sector table then spans the line table's
+    // range in sectors and the line table gets no bitmap of its own.  (Layer
+    // sectors outside the wave's exact sector range count for no shell, which
+    // intersects them with the wave's load sectors.)
+    bool w_lines_derived = false;
+    {
+        const int lr = H.log2_line - H.log2_sector;
+        const TableDesc& L = c.tab[T_WLINE];
+        if (!bad && dense_g[1] && keys_of[T_WSEC] > 0 && keys_of[T_WLINE] > 0 && lr >= 0 && lr <= 5) {
+            const uint64_t keys = (uint64_t)K.n_fields * ((uint64_t)L.span << lr);
+            if (keys < ((uint64_t)1 << 32)) {
+                c.tab[T_WSEC].umin = L.umin * ((int64_t)1 << lr);
+                c.tab[T_WSEC].span = L.span << lr;
+                keys_of[T_WSEC] = keys;
+                keys_of[T_WLINE] = 0;
+                w_lines_derived = true;
+            }
+        }
+    }
     // the layer pass keys its sectors with the wave table's layout and a tag
     if (!bad && c.smin >= 0 && keys_of[T_WSEC] > 0) {
         if (bits_for(keys_of[T_WSEC]) + c.tag_bits > 64) bad = 1;
@@ -669,7 +690,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         }
         bytes = (bytes + 255) & ~(int64_t)255;
     }
-    c.dense = (dense_g[0] ? 1 : 0) | (dense_g[1] ? 2 : 0);
+    c.dense = (dense_g[0] ? 1 : 0) | (dense_g[1] ? 2 : 0) | (w_lines_derived ? 4 : 0);
     if (bad) {
         c.status = bad == 2 ? -2 : -3;
         bytes = 0;
@@ -1232,8 +1253,9 @@ __device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, 
                         P.err |= 1;
                         continue;
                     }
-                    set_key_range(P, off_l + (uint32_t)band * words_l, (uint32_t)(ul_lo + ic.fl - 1),
-                                  (uint32_t)(ul_hi + ic.fl - 1));
+                    if (PASS == PASS_L || !(c.dense & 4))
+                        set_key_range(P, off_l + (uint32_t)band * words_l, (uint32_t)(ul_lo + ic.fl - 1),
+                                      (uint32_t)(ul_hi + ic.fl - 1));
                     if (PASS == PASS_W) {
                         set_key_range(P, off_s + (ic.st ? words_s : 0u), (uint32_t)(us_lo + ic.fs - 1),
                                       (uint32_t)(us_hi + ic.fs - 1));
@@ -1304,6 +1326,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     const uint32_t off_s = (uint32_t)((PASS == PASS_L ? TS.tag_off : TS.off) >> 2);
     const uint32_t off_l = (uint32_t)(TL.off >> 2);
     const uint32_t words_s = (uint32_t)TS.words, words_l = (uint32_t)TL.words;
+    // wave pass on bitmaps whose lines follow from its sectors: no line probes
+    const bool w_lines = !(PASS == PASS_W && DENSE && (c.dense & 4));
     // wave and layer passes: row order of their blocks; layer band
     // thresholds in recency order
     RowOrder ro;
@@ -1475,15 +1499,15 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         if (DENSE) {
                             const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
                             const uint32_t kl = (uint32_t)(ul + readlane64(ic.fl, q) - 1);
-                            WordProbe a, b;
+                            WordProbe a, b = {0ull, 0u, 0u, 0u, false};
                             if (FAST) {
                                 // every valid key is in range unless the item
                                 // reports an error: the valid lanes give the range
                                 a = word_probe_runs(P, bs + (st ? words_s : 0u), act, ks, vmask);
-                                b = word_probe_runs(P, bl, act, kl, vmask);
+                                if (w_lines) b = word_probe_runs(P, bl, act, kl, vmask);
                             } else {
                                 a = word_probe(P, bs + (st ? words_s : 0u), act, ks);
-                                b = word_probe(P, bl, act, kl);
+                                if (w_lines) b = word_probe(P, bl, act, kl);
                             }
                             probes_issued();
                             word_commit(P, a);
@@ -1762,7 +1786,12 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
     int64_t local = item - W->item_start;
     int64_t i0 = local * W->per_item;
     int64_t i1 = i0 + W->per_item < W->n_units ? i0 + W->per_item : W->n_units;
-    int64_t n0 = 0, n1 = 0, sh[3] = {0, 0, 0}, ll[3] = {0, 0, 0};
+    int64_t n0 = 0, n1 = 0, n2 = 0, sh[3] = {0, 0, 0}, ll[3] = {0, 0, 0};
+    // wave lines counted from the wave's sectors: groups of r = line / sector
+    // bits, aligned in every word
+    const bool lines_from_secs = q == T_WSEC && (c.dense & 4) != 0;
+    const int r_secs = lines_from_secs ? (int)(T.span / c.tab[T_WLINE].span) : 1;
+    const unsigned group_mask = r_secs >= 32 ? 1u : 0xffffffffu / ((1u << r_secs) - 1u);
     if (T.words > 0) {
         // bitmaps: popcounts, and the layer bands in recency order
         const unsigned* bm = (const unsigned*)(arena + T.off);
@@ -1771,9 +1800,14 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
         const unsigned* bands = q == T_WSEC && T.tag_off >= 0 ? (const unsigned*)(arena + T.tag_off) : nullptr;
         for (int64_t i = i0 + lane; i < i1; i += kLanes) {
             if (q == T_WSEC) {
-                const unsigned ld = bm[i];
+                const unsigned ld = bm[i], st = bm[nw + i];
                 n0 += __popc(ld);
-                n1 += __popc(bm[nw + i]);
+                n1 += __popc(st);
+                if (lines_from_secs) {
+                    unsigned x = ld | st;
+                    for (int k = 1; k < r_secs; k <<= 1) x |= x >> k;
+                    n2 += __popc(x & group_mask);
+                }
                 if (bands) {
                     unsigned acc = 0;
 #pragma unroll
@@ -1833,6 +1867,7 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
     }
     n0 = wave_sum64(n0);
     n1 = wave_sum64(n1);
+    n2 = wave_sum64(n2);
     for (int d = 0; d < 3; d++) {
         sh[d] = wave_sum64(sh[d]);
         ll[d] = wave_sum64(ll[d]);
@@ -1845,6 +1880,7 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
         else if (q == T_WSEC) {
             atomicAdd(&cc->fpld_W, (unsigned long long)n0);
             atomicAdd(&cc->comp_st_W, (unsigned long long)n1);
+            if (lines_from_secs) atomicAdd(&cc->lines_W, (unsigned long long)n2);
             for (int d = 0; d < 3; d++)
                 if (sh[d]) atomicAdd(&cc->shell[d], (unsigned long long)sh[d]);
         } else {
