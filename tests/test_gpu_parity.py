@@ -79,6 +79,22 @@ def test_stencil_folding_and_elements(ctx, orc):
     check(ctx, orc, [(k, W.HW1, sp)], "stencil folds/elems")
 
 
+def test_line_and_sector_sizes(ctx, orc):
+    """Line/sector ratios of 1, 2, 8 and 128: on bitmaps the wave's lines are
+    counted from its sector bitmaps up to a ratio of 32, and keep a line
+    bitmap of their own above it."""
+    k = W.star_stencil(2)
+    specs = []
+    for i, (line, sector) in enumerate([(64, 64), (128, 64), (256, 32), (4096, 32)]):
+        hw = dict(W.HW1, line_bytes=line, sector_bytes=sector)
+        sp = W.lattice_space([(48, 32, 32)], min_threads=32, max_threads=512, fy=(1, 2), fz=(1,),
+                             elems=[4, 8])
+        n = ctx.space_size(ctx.register_kernel(k), ctx.register_hw(hw), sp)
+        sp["explicit"] = sorted(random.Random(40 + i).sample(range(n), 12))
+        specs.append((k, hw, sp))
+    check(ctx, orc, specs, "line/sector sizes")
+
+
 def test_lbm_small(ctx, orc):
     k = W.lbm_two_phase(8)
     sp = W.lattice_space([(32, 32, 32)], min_threads=32, max_threads=1024, fy=(1, 2), fz=(1, 2),
