@@ -207,7 +207,10 @@ typedef struct {
                                    2048 words) */
     int32_t table_slack_log2;   /* HBM hash tables hold at least 2^slack slots per key bound (1..3) */
     int64_t item_evals;         /* address evaluations per work item of a workgroup (2^12 .. 2^22) */
-    int32_t groups_per_cu;      /* resident-loop workgroups per compute unit (1 .. 64) */
+    int32_t groups_per_cu;      /* evaluation and counting workgroups per compute unit (1 .. 1024);
+                                   each takes every (n_cu * groups_per_cu)-th work item, so grids
+                                   larger than what a CU holds at once let the hardware balance
+                                   uneven items */
     int32_t bitmap_log2;        /* the block pass's sets, and the wave and layer passes' sets, are
                                    kept as bitmaps instead of hash tables when every set of the
                                    group has a key range of at most 2^bitmap_log2 times the

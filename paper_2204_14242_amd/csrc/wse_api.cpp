@@ -232,7 +232,7 @@ struct wse_ctx {
     int table_slack = 1;
     int bitmap_log2 = 5;
     int row_ranges = 0;
-    int groups_per_cu = 16;
+    int groups_per_cu = 128;
     int64_t target_evals = 1 << 19;
     bool dirty_kernels = false, dirty_hws = false;
     bool progress = false;  // WSE_PROGRESS=1: one stderr line per arena round
@@ -1163,7 +1163,7 @@ static wse_status check_tuning(const wse_ctx* c, const wse_tuning* t)
         return fail(WSE_EINVAL, "lds_slots needs more LDS than a workgroup may allocate on this device");
     if (t->table_slack_log2 < 1 || t->table_slack_log2 > 3) return fail(WSE_EINVAL, "table_slack_log2 must be 1..3");
     if (t->item_evals < (1 << 12) || t->item_evals > (1 << 22)) return fail(WSE_EINVAL, "item_evals must be 2^12..2^22");
-    if (t->groups_per_cu < 1 || t->groups_per_cu > 64) return fail(WSE_EINVAL, "groups_per_cu must be 1..64");
+    if (t->groups_per_cu < 1 || t->groups_per_cu > 1024) return fail(WSE_EINVAL, "groups_per_cu must be 1..1024");
     if (t->bitmap_log2 < 0 || t->bitmap_log2 > 8) return fail(WSE_EINVAL, "bitmap_log2 must be 0..8");
     if (t->row_ranges != 0 && t->row_ranges != 1) return fail(WSE_EINVAL, "row_ranges must be 0 or 1");
     if (t->pad != 0) return fail(WSE_EINVAL, "pad must be 0");
@@ -1269,7 +1269,7 @@ extern "C" wse_status wse_autotune(wse_ctx* c, const wse_space* spaces, int32_t 
     const int lds_c[3] = {1024, 2048, 4096};
     const int64_t item_c[3] = {1 << 17, 1 << 19, 1 << 21};
     const int slack_c[2] = {1, 2};
-    const int groups_c[3] = {8, 16, 32};
+    const int groups_c[3] = {32, 128, 512};
     const int bitmap_c[3] = {0, 3, 6};
     for (int param = 0; param < 5; param++) {
         int n_c = param == 2 ? 2 : 3;

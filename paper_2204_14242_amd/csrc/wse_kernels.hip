@@ -1665,6 +1665,9 @@ __global__ __launch_bounds__(256, LATTICE_BITMAP ? 7 : 1) void k_eval(const Work
     const WorkEntry* work = work_all + rd->first[which];
     const int n_work = rd->n_work[which];
     const int64_t n_items = rd->items[which];
+    // workgroups beyond the round's items have nothing to do (the grid is
+    // sized for the largest rounds)
+    if ((int64_t)blockIdx.x >= n_items) return;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int llog = 31 - __clz(lds_slots);
     const int wlog = LATTICE_BITMAP ? kLatticeCacheLog2 : llog + 1;
