@@ -230,7 +230,7 @@ struct wse_ctx {
     // tuning
     int lds_slots = 2048;
     int table_slack = 1;
-    int bitmap_log2 = 5;
+    int bitmap_log2 = 8;
     int row_ranges = 0;
     int groups_per_cu = 128;
     int64_t target_evals = 1 << 19;
@@ -1270,7 +1270,7 @@ extern "C" wse_status wse_autotune(wse_ctx* c, const wse_space* spaces, int32_t 
     const int64_t item_c[3] = {1 << 17, 1 << 19, 1 << 21};
     const int slack_c[2] = {1, 2};
     const int groups_c[3] = {32, 128, 512};
-    const int bitmap_c[3] = {0, 3, 6};
+    const int bitmap_c[3] = {0, 4, 6};
     for (int param = 0; param < 5; param++) {
         int n_c = param == 2 ? 2 : 3;
         for (int v = 0; v < n_c; v++) {
