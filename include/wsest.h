@@ -199,7 +199,9 @@ wse_status wse_estimate(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces,
 /* ----------------------------------------------------------------- tuning */
 
 /* Launch and table-sizing parameters of the evaluation kernels.  They
- * change speed only: every result is identical under every tuning. */
+ * change speed only: every result is identical under every tuning.  A new
+ * context starts from lds_slots 2048, table_slack_log2 1, item_evals 2^19,
+ * groups_per_cu 128, bitmap_log2 8, row_ranges 0. */
 typedef struct {
     int32_t lds_slots;          /* slots of each of a workgroup's two LDS hash sets, and half the
                                    entries of its bitmap word cache: 1024, 2048 or 4096 (the wave and
