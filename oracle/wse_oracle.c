@@ -261,7 +261,6 @@ static int64_t fmod_pos(int64_t a, int64_t b)
 }
 
 #define ADDR_LIMIT ((__int128)1 << 62)
-#define UNIT_LIMIT ((int64_t)1 << 47)
 
 /* byte address of expression e for the thread (bid, tid) */
 static int64_t addr_of(cfg* c, const expr* e, const int64_t* bid, const int64_t* tid)
@@ -291,14 +290,42 @@ static int64_t addr_of(cfg* c, const expr* e, const int64_t* bid, const int64_t*
     return (int64_t)a;
 }
 
-/* key of (field, unit): fields never alias, so the field is part of the key */
-static uint64_t key_of(cfg* c, int64_t f, int64_t unit)
+/* Key of a unit (sector, line) inside its field's set.  Every address lies
+ * in [-2^62, 2^62) (else the configuration is out of range), so every unit
+ * of a granularity of one byte or more does too, and unit + 2^62 is an
+ * order-preserving unsigned key. */
+static uint64_t unit_key(int64_t unit) { return (uint64_t)unit + ((uint64_t)1 << 62); }
+
+/* One set per field: fields never alias (Sec. 4.3), so a (field, unit) pair
+ * is distinct from every pair of another field; the count of a set of pairs
+ * is the sum of the per-field counts. */
+typedef struct {
+    kset* f;
+    int64_t n;
+} fset;
+
+static void fset_init(fset* s, int64_t n_fields)
 {
-    if (unit >= UNIT_LIMIT || unit < -UNIT_LIMIT || f < 0 || f >= 65536) {
-        c->err = ORC_ERANGE;
-        return 0;
-    }
-    return ((uint64_t)f << 48) | (uint64_t)(unit + UNIT_LIMIT);
+    s->n = n_fields;
+    s->f = (kset*)calloc((size_t)(n_fields > 0 ? n_fields : 1), sizeof(kset));
+    if (!s->f) abort();
+}
+
+static void fset_add(fset* s, int64_t f, int64_t unit, int64_t tag) { kset_add(&s->f[f], unit_key(unit), tag); }
+
+static int64_t fset_size(fset* s)
+{
+    int64_t n = 0;
+    for (int64_t f = 0; f < s->n; f++) n += kset_size(&s->f[f]);
+    return n;
+}
+
+static void fset_free(fset* s)
+{
+    for (int64_t f = 0; f < s->n; f++) kset_free(&s->f[f]);
+    free(s->f);
+    s->f = NULL;
+    s->n = 0;
 }
 
 /* thread t (linear, x fastest) of block k: coordinates and validity */
@@ -643,29 +670,29 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
     r->up_st_B = wb.up_st;
     r->l1_cycles_B = wb.cycles;
     {
-        kset sec, lin;
-        kset_init(&sec);
-        kset_init(&lin);
+        fset sec, lin;
+        fset_init(&sec, K->n_fields);
+        fset_init(&lin, K->n_fields);
         for (int64_t t = 0; t < c.P; t++) {
             if (!thread_at(&c, kB, t, bid, tid)) continue;
             for (int64_t e = 0; e < c.nE; e++) {
                 if (c.ex[e].st) continue;
                 int64_t a = addr_of(&c, &c.ex[e], bid, tid);
-                kset_add(&sec, key_of(&c, c.ex[e].f, floor_div(a, H->sector_bytes)), 0);
-                kset_add(&lin, key_of(&c, c.ex[e].f, floor_div(a, H->line_bytes)), 0);
+                fset_add(&sec, c.ex[e].f, floor_div(a, H->sector_bytes), 0);
+                fset_add(&lin, c.ex[e].f, floor_div(a, H->line_bytes), 0);
             }
         }
-        r->comp_ld_B = kset_size(&sec);
-        r->lines_ld_B = kset_size(&lin);
-        kset_free(&sec);
-        kset_free(&lin);
+        r->comp_ld_B = fset_size(&sec);
+        r->lines_ld_B = fset_size(&lin);
+        fset_free(&sec);
+        fset_free(&lin);
     }
 
     /* ---- wave footprint (Sec. 4.4) ---- */
-    kset fpld, fpst, lw;
-    kset_init(&fpld);
-    kset_init(&fpst);
-    kset_init(&lw);
+    fset fpld, fpst, lw;
+    fset_init(&fpld, K->n_fields);
+    fset_init(&fpst, K->n_fields);
+    fset_init(&lw, K->n_fields);
     int64_t lanes_W = 0;
     warpstats wsw;
     memset(&wsw, 0, sizeof(wsw));
@@ -676,20 +703,19 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
             lanes_W++;
             for (int64_t e = 0; e < c.nE; e++) {
                 int64_t a = addr_of(&c, &c.ex[e], bid, tid);
-                uint64_t ks = key_of(&c, c.ex[e].f, floor_div(a, H->sector_bytes));
-                kset_add(c.ex[e].st ? &fpst : &fpld, ks, 0);
-                kset_add(&lw, key_of(&c, c.ex[e].f, floor_div(a, H->line_bytes)), 0);
+                fset_add(c.ex[e].st ? &fpst : &fpld, c.ex[e].f, floor_div(a, H->sector_bytes), 0);
+                fset_add(&lw, c.ex[e].f, floor_div(a, H->line_bytes), 0);
             }
         }
     }
     r->blocks_W = w1 - w0;
     r->lups_W = lanes_W * lups_per_thread;
-    r->fpld_W = kset_size(&fpld);
-    r->comp_st_W = kset_size(&fpst);
-    r->lines_W = kset_size(&lw);
+    r->fpld_W = fset_size(&fpld);
+    r->comp_st_W = fset_size(&fpst);
+    r->lines_W = fset_size(&lw);
     r->up_st_W = wsw.up_st;
-    kset_free(&fpst);
-    kset_free(&lw);
+    fset_free(&fpst);
+    fset_free(&lw);
 
     /* ---- layer-condition thread sets (Sec. 4.4.2) ----
      * C_d = { block(t - e_d) : t valid in the wave, t_d >= 1, block < w0 };
@@ -714,41 +740,36 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
     }
     if (smin >= 0) {
         /* every line of [smin, w0) tagged with the latest block touching it;
-         * every sector, restricted to the key range of the wave's load
-         * footprint (nothing outside it can be a wave sector) */
-        uint64_t lo = 0, hi = 0;
-        int64_t nfp = fpld.n;
-        if (nfp > 0) {
-            lo = fpld.a[0].key;
-            hi = fpld.a[nfp - 1].key;
-        }
-        kset ll, ls;
-        kset_init(&ll);
-        kset_init(&ls);
+         * every sector of a field, restricted to the key range of the wave's
+         * load footprint in that field (nothing outside it can be a wave
+         * sector) */
+        const int64_t nf = K->n_fields;
+        fset ll, ls;
+        fset_init(&ll, nf);
+        fset_init(&ls, nf);
         for (int64_t k = smin; k < w0; k++)
             for (int64_t t = 0; t < c.P; t++) {
                 if (!thread_at(&c, k, t, bid, tid)) continue;
                 for (int64_t e = 0; e < c.nE; e++) {
+                    const int64_t f = c.ex[e].f;
                     int64_t a = addr_of(&c, &c.ex[e], bid, tid);
-                    kset_add(&ll, key_of(&c, c.ex[e].f, floor_div(a, H->line_bytes)), k);
-                    uint64_t ks = key_of(&c, c.ex[e].f, floor_div(a, H->sector_bytes));
-                    if (nfp > 0 && ks >= lo && ks <= hi) kset_add(&ls, ks, k);
+                    fset_add(&ll, f, floor_div(a, H->line_bytes), k);
+                    const kset* fp = &fpld.f[f];
+                    uint64_t ks = unit_key(floor_div(a, H->sector_bytes));
+                    if (fp->n > 0 && ks >= fp->a[0].key && ks <= fp->a[fp->n - 1].key)
+                        kset_add(&ls.f[f], ks, k);
                 }
             }
-        kset_compact(&ll);
-        kset_compact(&ls);
+        for (int64_t f = 0; f < nf; f++) {
+            kset_compact(&ll.f[f]);
+            kset_compact(&ls.f[f]);
+        }
         for (int d = 0; d < 3; d++) {
             if (sd[d] < 0) continue;
             int64_t cnt = 0;
-            for (int64_t q = 0; q < ll.n; q++) cnt += ll.a[q].tag >= sd[d];
+            for (int64_t f = 0; f < nf; f++)
+                for (int64_t q = 0; q < ll.f[f].n; q++) cnt += ll.f[f].a[q].tag >= sd[d];
             r->lines_L[d] = cnt;
-        }
-        /* last[s] = latest layer block touching wave load sector s, or -1 */
-        int64_t* last = (int64_t*)malloc((size_t)(nfp > 0 ? nfp : 1) * sizeof(int64_t));
-        int64_t j = 0;
-        for (int64_t q = 0; q < nfp; q++) {
-            while (j < ls.n && ls.a[j].key < fpld.a[q].key) j++;
-            last[q] = (j < ls.n && ls.a[j].key == fpld.a[q].key) ? ls.a[j].tag : -1;
         }
         /* recency order: non-empty sets by s_d descending, ties x < y < z */
         int ord[3], no = 0;
@@ -761,21 +782,25 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
                     ord[a] = ord[b2];
                     ord[b2] = t;
                 }
-        for (int a = 0; a < no; a++) {
-            int d = ord[a];
-            int64_t cnt = 0;
-            for (int64_t q = 0; q < nfp; q++) {
-                int in_d = last[q] >= sd[d];
-                int in_prev = a > 0 && last[q] >= sd[ord[a - 1]];
-                cnt += in_d && !in_prev;
+        for (int64_t f = 0; f < nf; f++) {
+            const kset* fp = &fpld.f[f];
+            const kset* lf = &ls.f[f];
+            /* latest layer block touching each wave load sector of the field, or -1 */
+            int64_t j = 0;
+            for (int64_t q = 0; q < fp->n; q++) {
+                while (j < lf->n && lf->a[j].key < fp->a[q].key) j++;
+                int64_t last = (j < lf->n && lf->a[j].key == fp->a[q].key) ? lf->a[j].tag : -1;
+                for (int a = 0; a < no; a++) {
+                    int in_d = last >= sd[ord[a]];
+                    int in_prev = a > 0 && last >= sd[ord[a - 1]];
+                    r->shell[ord[a]] += in_d && !in_prev;
+                }
             }
-            r->shell[d] = cnt;
         }
-        free(last);
-        kset_free(&ll);
-        kset_free(&ls);
+        fset_free(&ll);
+        fset_free(&ls);
     }
-    kset_free(&fpld);
+    fset_free(&fpld);
     free(c.ex);
     if (c.err) {
         orc_result keep = *r;

@@ -436,3 +436,186 @@ def test_invalid_configs_are_reported(orc):
     # block larger than a CU can hold
     r = one(orc, k, with_hw(W.HW1, max_threads_per_cu=512), single_lattice_space((1024, 1, 1), (64, 64, 64), elem=8))
     assert r["status"] == -1
+
+
+# --------------------------------------------------------------------------
+# which hit-rate function prices which term (Sec. 4.5: four separate fits;
+# the x layer set takes the y fit).  Constant fits (b = 0) with distinct
+# values make any swap of two fits change a volume.
+# --------------------------------------------------------------------------
+
+FIT_A = {"fit_l1": (0.1, 0.0, 0.0), "fit_l2_y": (0.3, 0.0, 0.0), "fit_l2_z": (0.7, 0.0, 0.0),
+         "fit_l2_store": (0.9, 0.0, 0.0)}
+
+
+def star_kernel(offsets):
+    """Lattice kernel loading `src` at the given offsets and storing `dst` at 0."""
+    return {"kind": "lattice", "fields": [(8, 0), (8, 0)], "ghost": 0,
+            "accesses": [(0, 0) + tuple(o) for o in offsets] + [(1, 1, 0, 0, 0)], "flops_per_lup": 0.0}
+
+
+def axis_star(radius, axes):
+    offs = [(0, 0, 0)]
+    for k in range(1, radius + 1):
+        for s in (1, -1):
+            for d in axes:
+                o = [0, 0, 0]
+                o[d] = s * k
+                offs.append(tuple(o))
+    return star_kernel(offs)
+
+
+def test_x_layer_set_closed_form_uses_the_y_fit(orc):
+    # 1D range-4 star on 4096 points, (64,1,1) blocks, waves of N = 8 blocks:
+    # the middle wave loads x in [64 w0 - 4, 64 w1 + 4), 16 N + 2 sectors, and
+    # its x layer set (block w0 - 1) shares the 2 sectors around x = 64 w0
+    hw = with_hw(W.HW1, n_cu=4, **FIT_A)
+    r = one(orc, axis_star(4, [0]), hw, single_lattice_space((64, 1, 1), (4096, 1, 1), elem=8))
+    N = 8
+    assert r["blocks_W"] == N and list(r["s_layer"]) == [31, -1, -1]
+    assert r["fpld_W"] == 16 * N + 2 and list(r["shell"]) == [2, 0, 0]
+    assert r["up_st_W"] == r["comp_st_W"] == 16 * N
+    assert r["R_L"][0] == 0.3                      # the y fit's value
+    assert r["v_dram_ld"] == pytest.approx(16 * N + 0.7 * 2)
+
+
+def test_y_layer_set_closed_form(orc):
+    # 2D range-4 star (x and y axes) on 256 x 2048 x 1 with (256,1,1) blocks:
+    # the middle wave is rows 1024..1535 and loads rows 1020..1539 (520 rows
+    # of 64 sectors); its y layer set, row 1023, shares rows 1020..1027
+    hw = with_hw(W.HW1, **FIT_A)
+    r = one(orc, axis_star(4, [0, 1]), hw, single_lattice_space((256, 1, 1), (256, 2048, 1), elem=8))
+    assert r["blocks_W"] == 512 and list(r["s_layer"]) == [-1, 1023, -1]
+    assert r["fpld_W"] == 520 * 64 and list(r["shell"]) == [0, 8 * 64, 0]
+    assert r["lines_L"][1] == 9 * 16 + 16         # 9 source rows and the stored row, 16 lines each
+    assert r["R_L"][1] == 0.3
+    assert r["v_dram_ld"] == pytest.approx(512 * 64 + 0.7 * 512)
+
+
+@pytest.mark.parametrize("d", [1, 4])
+def test_z_layer_set_closed_form(orc, d):
+    # full-plane waves of d planes: the z layer set shares 8 planes (Sec. 4.4.2)
+    hw = with_hw(plane_wave_hw(d, 1), **FIT_A)
+    r = one(orc, W.star_stencil(4), hw, single_lattice_space((256, 1, 1), (256, 256, 256), elem=8))
+    assert r["shell"][2] == 8 * 16384 and r["R_L"][2] == 0.7
+    assert r["v_dram_ld"] == pytest.approx(d * 16384 + 0.3 * 8 * 16384)
+
+
+def test_fit_assignment_all_terms(orc):
+    # a wave that starts inside a row of blocks: x, y and z layer sets are all
+    # non-empty; every term takes its own fit
+    hw = with_hw(W.HW1, n_cu=107, **FIT_A)
+    sp = single_lattice_space((32, 4, 8), (256, 256, 256), elem=8)
+    r = one(orc, W.star_stencil(4), hw, sp)
+    assert list(r["s_layer"]) == [8131, 8124, 7620]
+    assert (r["shell"] > 0).all()
+    assert r["R_l1"] == 0.1 and r["R_st"] == 0.9
+    assert list(r["R_L"]) == [0.3, 0.3, 0.7]
+    comp, up = float(r["comp_ld_B"]), float(r["up_ld_B"])
+    assert r["v_l2l1_ld"] == comp + (1.0 - 0.1) * (up - comp)
+    new = float(r["fpld_W"] - r["shell"].sum())
+    want = new
+    for d, R in enumerate((0.3, 0.3, 0.7)):
+        want = want + (1.0 - R) * float(r["shell"][d])
+    want = want + (1.0 - 0.9) * float(r["up_st_W"] - r["comp_st_W"])
+    assert r["v_dram_ld"] == want
+    # swapping two fits moves the volumes: every fit is used where it should be
+    for a, b in (("fit_l2_y", "fit_l2_z"), ("fit_l1", "fit_l2_store"), ("fit_l2_y", "fit_l2_store")):
+        sw = dict(hw)
+        sw[a], sw[b] = hw[b], hw[a]
+        r2 = one(orc, W.star_stencil(4), sw, sp)
+        assert (r2["v_l2l1_ld"], r2["v_dram_ld"]) != (r["v_l2l1_ld"], r["v_dram_ld"]), (a, b)
+
+
+# --------------------------------------------------------------------------
+# representable range: every evaluated address lies in [-2^62, 2^62)
+# --------------------------------------------------------------------------
+
+def range_kernel(align, sign=1):
+    return W.affine_kernel([(8, align)], [load_expr(0, cg=(sign, 0, 0)), load_expr(0, c0=1, cg=(sign, 0, 0), store=1)])
+
+
+def range_space():
+    # blocks of 64 threads in x; grids of 1..4 blocks
+    sp = W.affine_space([(1, 1, 1), (2, 1, 1), (3, 1, 1), (4, 1, 1)], min_threads=64, max_threads=64)
+    sp["bx_exps"], sp["by_exps"], sp["bz_exps"] = [6], [0], [0]
+    return sp
+
+
+RANGE_HW = with_hw(W.HW1, n_cu=1, blocks_per_cu=1)
+
+
+def test_addresses_past_the_range_are_reported(orc):
+    # 8 B elements from 2^62 - 8 * 129: the load of gid g is at element g and
+    # the store at g + 1, so gids up to 127 stay inside and gid 128 leaves.
+    # With one block per wave, a grid of g blocks evaluates the blocks
+    # floor(g / 2) (centre block, middle wave) and the one before it (x layer
+    # set): grids of 1..3 blocks never evaluate gid 128 (a grid of 3 has
+    # block 2 out of range, but no set evaluates it); a grid of 4 does.
+    lim = 1 << 62
+    res, _ = orc.estimate(range_kernel(lim - 8 * 129), RANGE_HW, range_space(), n_threads=1)
+    assert [int(s) for s in res["status"]] == [0, 0, 0, -3]
+    bad = res[3]
+    assert bad["limiter"] == -1 and bad["perf"] == 0.0 and bad["fpld_W"] == 0
+    assert list(bad["shape"]) == [64, 1, 1] and list(bad["domain"]) == [4, 1, 1]
+    # the lower end: -2^62 itself is inside (the load of gid 127), one
+    # element below it is not (gid 128)
+    res, _ = orc.estimate(range_kernel(-lim + 8 * 127, sign=-1), RANGE_HW, range_space(), n_threads=1)
+    assert [int(s) for s in res["status"]] == [0, 0, 0, -3]
+
+
+def test_large_addresses_inside_the_range_count_normally(orc):
+    # addresses near 2^61, whose sector numbers exceed 2^47, count like the same
+    # kernel aligned at 0 (a shift by a multiple of the line size)
+    a, _ = orc.estimate(range_kernel(0), RANGE_HW, range_space(), n_threads=1)
+    b, _ = orc.estimate(range_kernel(1 << 61), RANGE_HW, range_space(), n_threads=1)
+    assert (b["status"] == 0).all()
+    for x, y in zip(a, b):
+        same_counts(x, y)
+
+
+# --------------------------------------------------------------------------
+# canonical configuration index: mixed radix over (domain, elem, fz, fy,
+# shape), slowest first; shapes by (log2 bx, log2 by, log2 bz) ascending
+# --------------------------------------------------------------------------
+
+def canonical_lattice(space):
+    shapes = [(a, b, c) for a in sorted(space["bx_exps"]) for b in sorted(space["by_exps"])
+              for c in sorted(space["bz_exps"]) if space["min_threads"] <= 2 ** (a + b + c) <= space["max_threads"]]
+    out = []
+    for dom in space["domains"]:
+        for el in sorted(space["elems"]):
+            for fz in sorted(space["fz"]):
+                for fy in sorted(space["fy"]):
+                    for (a, b, c) in shapes:
+                        out.append((tuple(dom), el, fy, fz, (2 ** a, 2 ** b, 2 ** c)))
+    return out
+
+
+def test_canonical_index_order_lattice(orc):
+    sp = W.lattice_space([(16, 16, 16), (32, 16, 8)], min_threads=32, max_threads=64, fy=(2, 1),
+                         fz=(4, 1), elems=[8, 4], exps=range(7))
+    want = canonical_lattice(sp)
+    assert len(want) == 2 * 2 * 2 * 2 * 49
+    res, _ = orc.estimate(W.star_stencil(1), W.HW1, sp, n_threads=8)
+    assert len(res) == len(want)
+    for i, (r, (dom, el, fy, fz, shape)) in enumerate(zip(res, want)):
+        assert r["index"] == i
+        assert (tuple(r["domain"]), int(r["elem"]), int(r["fold"][1]), int(r["fold"][2]),
+                tuple(r["shape"])) == (dom, el, fy, fz, shape), i
+    # an explicit subset comes back in the order given
+    pick = [700, 3, 391, 50]
+    sub, _ = orc.estimate(W.star_stencil(1), W.HW1, dict(sp, explicit=pick), n_threads=4)
+    assert [int(v) for v in sub["index"]] == pick
+    assert sub.tobytes() == res[pick].tobytes()
+
+
+def test_canonical_index_order_affine(orc):
+    grids = [(2, 1, 1), (1, 3, 1), (1, 1, 2)]
+    sp = W.affine_space(grids, min_threads=4, max_threads=8, exps=range(4))
+    shapes = [(2 ** a, 2 ** b, 2 ** c) for a in range(4) for b in range(4) for c in range(4)
+              if 4 <= 2 ** (a + b + c) <= 8]
+    want = [(g, s) for g in grids for s in shapes]
+    k = W.affine_kernel([(8, 0)], [load_expr(0, cg=(1, 7, 50))])
+    res, _ = orc.estimate(k, TINY_HW, sp, n_threads=4)
+    assert [(tuple(r["domain"]), tuple(r["shape"])) for r in res] == want
