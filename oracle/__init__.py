@@ -52,7 +52,8 @@ class _Kernel(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_fields", C.c_int32),
                 ("field_elem", C.POINTER(C.c_int64)), ("field_align", C.POINTER(C.c_int64)),
                 ("ghost", C.c_int64), ("n_items", C.c_int32),
-                ("items", C.POINTER(C.c_int64)), ("flops_per_lup", C.c_double)]
+                ("items", C.POINTER(C.c_int64)), ("flops_per_lup", C.c_double),
+                ("multidim", C.c_int32)]
 
 
 class _Hw(C.Structure):
@@ -134,6 +135,7 @@ def _marshal(kernel, hw, space):
     k.n_items = len(items)
     k.items = arr([v for it in items for v in it])
     k.flops_per_lup = float(kernel.get("flops_per_lup", 0.0))
+    k.multidim = 1 if (k.kind == 0 and kernel.get("address_space") == "multidim") else 0
 
     h = None
     if hw is not None:

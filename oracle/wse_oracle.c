@@ -245,6 +245,12 @@ typedef struct {
     int64_t nE;
     expr* ex;
     int err;                    /* ORC_ERANGE once an address or key is out of range */
+    /* multi-dimensional address space of the wave and layer sets: the
+     * smallest array coordinates any access of the configuration reaches,
+     * the number of rows (y values) per plane, and per granularity (0 sector,
+     * 1 line) the smallest x unit and the number of x units per row */
+    int md;
+    int64_t md_lo[3], md_ny, md_xu_lo[2], md_nxu[2];
 } cfg;
 
 static int64_t floor_div(int64_t a, int64_t b)
@@ -288,6 +294,33 @@ static int64_t addr_of(cfg* c, const expr* e, const int64_t* bid, const int64_t*
         return 0;
     }
     return (int64_t)a;
+}
+
+/* Unit of granularity index gi (0 sector, 1 line) that expression e of
+ * thread (bid, tid) touches in the wave and layer sets.  Linear addresses:
+ * floor(address / granularity).  Multi-dimensional address space (Sec.
+ * 4.4.1): the tuple (z, y, floor(x * elem / granularity)) of the point's
+ * array coordinates, numbered lexicographically (z slowest) over the
+ * coordinate box of the configuration, so that distinct tuples get distinct
+ * numbers and the field's alignment plays no part. */
+static int64_t wave_unit(cfg* c, const expr* e, const int64_t* bid, const int64_t* tid, int gi)
+{
+    const int64_t gran = gi == 0 ? c->H->sector_bytes : c->H->line_bytes;
+    if (!c->md) return floor_div(addr_of(c, e, bid, tid), gran);
+    int64_t gid[3];
+    for (int d = 0; d < 3; d++) gid[d] = bid[d] * c->b[d] + tid[d];
+    const int64_t x = gid[0] + e->v[0] + c->g;
+    const int64_t y = c->fold[1] * gid[1] + e->v[1] + c->g;
+    const int64_t z = c->fold[2] * gid[2] + e->v[2] + c->g;
+    const int64_t elem = c->elem ? c->elem : c->K->field_elem[e->f];
+    const int64_t xu = floor_div(x * elem, gran);
+    const __int128 key = ((__int128)(z - c->md_lo[2]) * c->md_ny + (y - c->md_lo[1])) * c->md_nxu[gi] +
+                         (xu - c->md_xu_lo[gi]);
+    if (key >= ADDR_LIMIT) {
+        c->err = ORC_ERANGE;
+        return 0;
+    }
+    return (int64_t)key;
 }
 
 /* Key of a unit (sector, line) inside its field's set.  Every address lies
@@ -397,6 +430,8 @@ typedef struct {
  * warps and instructions of distinct sectors (loads and stores apart), and,
  * if want_cycles, the L1 bank-conflict cycles of every lane group. */
 static void block_warp_stats(cfg* c, int64_t k, int want_cycles, int stores_only, warpstats* ws)
+/* (stores_only: the wave's warp-level store sectors, in the wave's address
+ * space; otherwise the representative block, in linear addresses) */
 {
     const orc_hw* H = c->H;
     int64_t W = H->warp_size, G = H->l1_group_lanes;
@@ -415,7 +450,8 @@ static void block_warp_stats(cfg* c, int64_t k, int want_cycles, int stores_only
             int64_t n = 0;
             for (int64_t t = w0; t < w1; t++) {
                 if (!thread_at(c, k, t, bid, tid)) continue;
-                buf[n++] = floor_div(addr_of(c, x, bid, tid), H->sector_bytes);
+                buf[n++] = stores_only ? wave_unit(c, x, bid, tid, 0)
+                                       : floor_div(addr_of(c, x, bid, tid), H->sector_bytes);
             }
             int64_t d = n_distinct(buf, n);
             if (x->st) ws->up_st += d;
@@ -656,6 +692,41 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
 
     expand(&c);
     r->n_expr = c.nE;
+    if (c.lattice && K->multidim) {
+        /* one element size per configuration: the override, or that of
+         * every field of the kernel */
+        int64_t elem = c.elem;
+        for (int64_t f = 0; f < K->n_fields && !c.elem; f++) {
+            const int64_t fe = K->field_elem[f];
+            if (elem == 0) elem = fe;
+            if (fe != elem) {
+                free(c.ex);
+                r->status = ORC_EINVAL;
+                return;
+            }
+        }
+        /* coordinate box of every point the configuration's threads access */
+        int64_t vlo[3], vhi[3];
+        for (int d = 0; d < 3; d++) {
+            vlo[d] = vhi[d] = c.ex[0].v[d];
+            for (int64_t e = 1; e < c.nE; e++) {
+                if (c.ex[e].v[d] < vlo[d]) vlo[d] = c.ex[e].v[d];
+                if (c.ex[e].v[d] > vhi[d]) vhi[d] = c.ex[e].v[d];
+            }
+        }
+        int64_t hi[3];
+        for (int d = 0; d < 3; d++) {
+            c.md_lo[d] = c.g + vlo[d];
+            hi[d] = c.g + c.fold[d] * (c.T[d] - 1) + vhi[d];
+        }
+        c.md_ny = hi[1] - c.md_lo[1] + 1;
+        for (int gi = 0; gi < 2; gi++) {
+            const int64_t gran = gi == 0 ? H->sector_bytes : H->line_bytes;
+            c.md_xu_lo[gi] = floor_div(c.md_lo[0] * elem, gran);
+            c.md_nxu[gi] = floor_div(hi[0] * elem, gran) - c.md_xu_lo[gi] + 1;
+        }
+        c.md = 1;
+    }
     int64_t lups_per_thread = c.fold[1] * c.fold[2];
     int64_t bid[3], tid[3];
 
@@ -702,9 +773,8 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
             if (!thread_at(&c, k, t, bid, tid)) continue;
             lanes_W++;
             for (int64_t e = 0; e < c.nE; e++) {
-                int64_t a = addr_of(&c, &c.ex[e], bid, tid);
-                fset_add(c.ex[e].st ? &fpst : &fpld, c.ex[e].f, floor_div(a, H->sector_bytes), 0);
-                fset_add(&lw, c.ex[e].f, floor_div(a, H->line_bytes), 0);
+                fset_add(c.ex[e].st ? &fpst : &fpld, c.ex[e].f, wave_unit(&c, &c.ex[e], bid, tid, 0), 0);
+                fset_add(&lw, c.ex[e].f, wave_unit(&c, &c.ex[e], bid, tid, 1), 0);
             }
         }
     }
@@ -752,10 +822,9 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
                 if (!thread_at(&c, k, t, bid, tid)) continue;
                 for (int64_t e = 0; e < c.nE; e++) {
                     const int64_t f = c.ex[e].f;
-                    int64_t a = addr_of(&c, &c.ex[e], bid, tid);
-                    fset_add(&ll, f, floor_div(a, H->line_bytes), k);
+                    fset_add(&ll, f, wave_unit(&c, &c.ex[e], bid, tid, 1), k);
                     const kset* fp = &fpld.f[f];
-                    uint64_t ks = unit_key(floor_div(a, H->sector_bytes));
+                    uint64_t ks = unit_key(wave_unit(&c, &c.ex[e], bid, tid, 0));
                     if (fp->n > 0 && ks >= fp->a[0].key && ks <= fp->a[fp->n - 1].key)
                         kset_add(&ls.f[f], ks, k);
                 }

@@ -48,6 +48,11 @@ typedef struct {
     int32_t n_items;
     const int64_t* items;
     double flops_per_lup;
+    /* 1: the wave and layer sets of a lattice kernel are counted in the
+     * multi-dimensional address space of Sec. 4.4.1: a point of field f at
+     * array coordinates (x, y, z) names the unit (f, z, y, floor(x*elem/g))
+     * of granularity g; the alignment plays no part.  0: linear addresses. */
+    int32_t multidim;
 } orc_kernel;
 
 /* Hardware description; fit[i] = (a, b, c) of R(O) = a*exp(-b*exp(c*O)) for

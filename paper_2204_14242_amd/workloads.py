@@ -134,6 +134,14 @@ def lbm_two_phase(elem=8):
             "flops_per_lup": 0.0}
 
 
+def lattice_kernel_from(accesses, n_fields=1, elem=8, align=0, ghost=0, address_space="linear"):
+    """A lattice kernel of the given accesses (field, is_store, ox, oy, oz)
+    over n_fields fields of one element size and alignment."""
+    return {"kind": "lattice", "fields": [(elem, align)] * n_fields, "ghost": ghost,
+            "accesses": [tuple(int(v) for v in a) for a in accesses], "flops_per_lup": 0.0,
+            "address_space": address_space}
+
+
 def four_point_2d(elem=8, align=0):
     """The paper's introductory 2D four-point stencil (Sec. 1.2):
     dst[0,0] = (src[1,0] + src[-1,0] + src[0,1] + src[0,-1]) / 4."""
@@ -197,6 +205,23 @@ def lbm_batched():
     return (lbm_two_phase(8), HW1,
             lattice_space([(256, 256, 256)], min_threads=32, max_threads=1024,
                           fy=(1, 2, 4, 8), fz=(1, 2, 4, 8), elems=[8]))
+
+
+LC_SCAN_XY = (128, 160, 192, 224, 256, 288, 320, 352, 384, 416, 448, 480, 512, 576, 640, 704,
+              768, 832, 896, 960, 1024)
+
+
+def layer_condition_scan(hw=None, xy=LC_SCAN_XY):
+    """Domain-size scan of the range-4 star stencil (Sec. 5.7, Fig. 20):
+    quadratic XY planes of growing extent at constant total volume, depth
+    z = 512*1024*1024 / (x*y) rounded to the nearest integer, fp64, every
+    block of 1024 threads (66 shapes, (1,1,1024) first and (1024,1,1)
+    last in canonical order), no folding: 21 x 66 = 1,386 configurations.  The hardware
+    defaults to the A100-shaped set whose 20 MB effective L2 the paper
+    discusses the scan against."""
+    doms = [(x, x, max(1, int(round(512 * 1024 * 1024 / (x * x))))) for x in xy]
+    return (star_stencil(4), H2 if hw is None else hw,
+            lattice_space(doms, min_threads=1024, max_threads=1024, elems=[8]))
 
 
 def stress_spaces(seed=5, total=1_000_000, max_space=None):

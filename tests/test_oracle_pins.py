@@ -619,3 +619,128 @@ def test_canonical_index_order_affine(orc):
     k = W.affine_kernel([(8, 0)], [load_expr(0, cg=(1, 7, 50))])
     res, _ = orc.estimate(k, TINY_HW, sp, n_threads=4)
     assert [(tuple(r["domain"]), tuple(r["shape"])) for r in res] == want
+
+
+# --------------------------------------------------------------------------
+# domain-size scan at constant volume (Sec. 5.7, Layer Condition Like
+# Phenomenon on GPUs, Fig. 20)
+# --------------------------------------------------------------------------
+
+def scan_index(space, dom_i, shape):
+    shapes = [(2 ** a, 2 ** b, 2 ** c) for a in space["bx_exps"] for b in space["by_exps"]
+              for c in space["bz_exps"] if space["min_threads"] <= 2 ** (a + b + c) <= space["max_threads"]]
+    return dom_i * len(shapes) + shapes.index(shape)
+
+
+def test_scan_keeps_the_volume_constant():
+    _, _, sp = W.layer_condition_scan()
+    for x, y, z in sp["domains"]:
+        assert x == y and abs(x * y * z - 512 * 1024 * 1024) <= x * y / 2
+
+
+def test_scan_z_layer_lines_of_one_plane_waves(orc):
+    # (512,2,1) blocks on the A100-shaped GPU: 216 blocks of 1024 threads per
+    # wave, less than one 512^2 plane, so the z layer set is the interval of
+    # one x*y plane of threads ending at the wave; its linear indices shifted by
+    # -4..4 planes are one contiguous range of 9 planes (plus 4 rows at either
+    # end for the y arms), and the store field adds one plane: lines_L[z] lies
+    # between 10 x^2 * 8 B / 128 B and (10 x^2 + 8 x) * 8 B / 128 B + 2
+    k, hw, sp = W.layer_condition_scan(xy=(480, 704, 1024))
+    for i, (x, _, _) in enumerate(sp["domains"]):
+        assert x * x >= 216 * 1024
+        r = one(orc, k, hw, dict(sp, explicit=[scan_index(sp, i, (512, 2, 1))]))
+        lo, hi = 10 * x * x * 8 // 128, (10 * x * x + 8 * x) * 8 // 128 + 2
+        assert lo <= r["lines_L"][2] <= hi, (x, r["lines_L"][2], lo, hi)
+
+
+def test_scan_deeper_blocks_run_out_of_capacity_earlier(orc):
+    # the z layer set's allocation, and with it O_L[z], grows with the blocks'
+    # z extent at every plane size (Sec. 5.7: deeper blocks need more than the
+    # nine layers of the sequential layer condition)
+    k, hw, sp = W.layer_condition_scan(xy=(256, 576))
+    shapes = [(512, 2, 1), (256, 2, 2), (128, 2, 4), (64, 2, 8)]
+    for i in range(2):
+        res, _ = orc.estimate(k, hw, dict(sp, explicit=[scan_index(sp, i, s) for s in shapes]), n_threads=4)
+        o = list(res["O_L"][:, 2])
+        assert all(a < b for a, b in zip(o, o[1:])), (sp["domains"][i], o)
+
+
+# --------------------------------------------------------------------------
+# multi-dimensional address space of the wave and layer sets (Sec. 4.4.1,
+# Implicit Thread and Address Sets)
+# --------------------------------------------------------------------------
+
+def md(kernel):
+    return dict(kernel, address_space="multidim")
+
+
+# one wave holds the whole (X, Y, 1) domain: blocks of 128 threads in x
+WIDE_HW = with_hw(W.HW1, n_cu=64, blocks_per_cu=1)
+
+
+def plane_space(X, Y):
+    return single_lattice_space((128, 1, 1), (X, Y, 1))
+
+
+def test_multidim_keeps_wrapped_coordinates_apart(orc):
+    # The paper's example: in a 100-wide array, (x + 100, y) and (x, y + 1)
+    # are one linear address but two tuples of the multi-dimensional space.
+    A = W.lattice_kernel_from([(0, 0, 100, 0, 0)])
+    B = W.lattice_kernel_from([(0, 0, 0, 1, 0)])
+    AB = W.lattice_kernel_from([(0, 0, 100, 0, 0), (0, 0, 0, 1, 0)])
+    sp = plane_space(100, 20)
+    lin = {n: one(orc, k, WIDE_HW, sp) for n, k in (("A", A), ("B", B), ("AB", AB))}
+    mdr = {n: one(orc, md(k), WIDE_HW, sp) for n, k in (("A", A), ("B", B), ("AB", AB))}
+    assert lin["AB"]["blocks_W"] == 20 and lin["AB"]["s_layer"].tolist() == [-1, -1, -1]
+    # linear: the two accesses name the same 2,000 addresses
+    for key in ("fpld_W", "lines_W"):
+        assert lin["AB"][key] == lin["A"][key] == lin["B"][key], key
+    assert lin["AB"]["fpld_W"] == 2000 * 8 // 32
+    # multi-dimensional: the two accesses share no element and no sector
+    # (sector 24 of a row holds x = 96..99 of B, sector 25 x = 100..103 of A);
+    # rows 1..19 hold B's x = 96..99 and A's x = 100..111 in their line 6
+    assert mdr["AB"]["fpld_W"] == mdr["A"]["fpld_W"] + mdr["B"]["fpld_W"] == 1000
+    assert mdr["AB"]["lines_W"] == mdr["A"]["lines_W"] + mdr["B"]["lines_W"] - 19
+
+
+@pytest.mark.parametrize("X", [100, 96, 64, 33])
+def test_multidim_rows_start_on_their_own_line(orc, X):
+    # Every row of X fp64 values takes ceil(8 X / 128) lines and ceil(8 X / 32)
+    # sectors of its own; in the linear space, aligned at 0, the 20 rows are
+    # one contiguous range of 160 X bytes.
+    k = W.lattice_kernel_from([(0, 0, 0, 0, 0)])
+    sp = plane_space(X, 20)
+    r_md = one(orc, md(k), WIDE_HW, sp)
+    r_lin = one(orc, k, WIDE_HW, sp)
+    assert r_md["lines_W"] == 20 * -(-8 * X // 128)
+    assert r_md["fpld_W"] == 20 * -(-8 * X // 32)
+    assert r_lin["lines_W"] == -(-160 * X // 128)
+    assert r_lin["fpld_W"] == -(-160 * X // 32)
+
+
+def test_multidim_ignores_the_alignment(orc):
+    # every wave and layer count is the same for any field alignment, and the
+    # block pass keeps linear addresses (its counts move with the alignment)
+    sp = single_lattice_space((16, 4, 4), (96, 40, 40))
+    a = one(orc, md(W.star_stencil(2, align=0)), W.H2, sp)
+    b = one(orc, md(W.star_stencil(2, align=24)), W.H2, sp)
+    for key in ("fpld_W", "comp_st_W", "lines_W", "up_st_W", "lines_L", "shell", "s_layer"):
+        assert np.array_equal(a[key], b[key]), key
+    assert a["lines_W"] > 0 and (a["lines_L"] > 0).any()
+    c_lin = one(orc, W.star_stencil(2, align=0), W.H2, sp)
+    d_lin = one(orc, W.star_stencil(2, align=24), W.H2, sp)
+    assert c_lin["comp_ld_B"] == a["comp_ld_B"] and d_lin["comp_ld_B"] == b["comp_ld_B"]
+    assert c_lin["fpld_W"] != d_lin["fpld_W"]
+
+
+def test_multidim_equals_linear_without_wraps(orc):
+    # no x offsets, ghost layers for the y and z arms, rows of 64 fp64 = 4
+    # whole lines aligned at 0: no row shares a line and no coordinate wraps,
+    # so both spaces count the same sets
+    acc = [(0, 0, 0, 0, 0)] + [(0, 0, 0, s * d, 0) for d in (1, 2) for s in (1, -1)] + \
+          [(0, 0, 0, 0, s * d) for d in (1, 2) for s in (1, -1)] + [(1, 1, 0, 0, 0)]
+    k = W.lattice_kernel_from(acc, n_fields=2, ghost=2)
+    sp = single_lattice_space((32, 4, 2), (60, 32, 32))
+    a = one(orc, k, W.H2, sp)
+    b = one(orc, md(k), W.H2, sp)
+    assert a.tobytes() == b.tobytes()
