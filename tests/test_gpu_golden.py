@@ -1,0 +1,88 @@
+"""Parity against stored oracle values at the workloads' full sizes.
+
+tests/golden/make_golden.py ran the CPU oracle (and nothing else) on seeded
+stratified samples of the three large workloads: about 2 % of the
+40,160-configuration stencil space and of the 4,016-configuration LBM space
+(stratified per domain and folding, plus each large domain's heaviest
+configurations, above 10^9 evaluations) and 10 configurations of each of
+210 spaces of the 10^6-configuration stress batch.  Each file holds
+"chunks": one explicit subset of one space per oracle call.  Here every
+chunk of a file becomes one space of a single batched estimate, in the
+benchmark's launch configuration, and every record must match byte for
+byte, ranks (within each chunk) included."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2204_14242_amd import workloads as W
+from gpu_common import assert_same, gpu_available
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_2204_14242_amd import wsest
+    c = wsest.Context(0, arena_bytes=32 << 30)
+    yield c
+    c.close()
+
+
+def load(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} has not been generated")
+    return np.load(path)
+
+
+def run_chunks(ctx, g, kernel_hw_space, label, min_configs):
+    from paper_2204_14242_amd import wsest
+    off, ex = g["offsets"], g["explicit"]
+    specs, reg = [], {}
+    for c in range(len(off) - 1):
+        k, hw, sp = kernel_hw_space(int(g["space"][c]))
+        key = (id(k), id(hw))
+        if key not in reg:
+            reg[key] = (ctx.register_kernel(k), ctx.register_hw(hw))
+        kid, hid = reg[key]
+        specs.append((kid, hid, dict(sp, explicit=[int(v) for v in ex[off[c]:off[c + 1]]])))
+    want, wrank = g["results"], g["rank"]
+    assert len(want) >= min_configs
+    say(f"case {label}: {len(want)} configurations in {len(specs)} chunks, one batched call")
+    got, grank = ctx.estimate(specs, mode=wsest.BATCHED)
+    assert_same(got, want, grank, wrank, label)
+    return got, ctx.last_evals(len(got))
+
+
+def test_stencil_batched_stored_sample(ctx):
+    k, hw, sp = W.stencil_batched()
+    got, evals = run_chunks(ctx, load("stencil_batched_sample.npz"), lambda s: (k, hw, sp),
+                            "stencil batched stored sample", 800)
+    # every domain size, and the heavy tail the benchmark's time sits in
+    assert len({tuple(d) for d in got["domain"].tolist()}) == 5
+    assert (evals > 1e9).sum() >= 5, sorted(evals)[-8:]
+
+
+def test_lbm_batched_stored_sample(ctx):
+    k, hw, sp = W.lbm_batched()
+    got, evals = run_chunks(ctx, load("lbm_batched_sample.npz"), lambda s: (k, hw, sp),
+                            "lbm batched stored sample", 80)
+    assert len({tuple(f) for f in got["fold"].tolist()}) == 16
+    assert (evals > 1e9).sum() >= 1
+
+
+def test_stress_stored_sample(ctx):
+    spaces = W.stress_spaces(seed=5, total=1_000_000)
+    run_chunks(ctx, load("stress_sample.npz"), lambda s: spaces[s], "stress stored sample", 2000)
