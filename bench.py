@@ -5,8 +5,12 @@ block shapes 2^a x 2^b x 2^c with 32..1024 threads x folding {1,2,4,8} in y
 and z x cubic domains 64^3..1024^3 x fp32/fp64 elements (40,160
 configurations), results and ranks kept in device memory.  Prints one JSON
 line: configurations estimated per second, the evaluation kernel's
-achieved integer-op rate against the VALU peak, and the CPU oracle's rate
-on a bounded sample of the same workload.
+achieved integer-op rate against the VALU peak, the CPU oracle's rate on a
+bounded sample of the same workload, and beside them one timed estimate of
+each other workload (the plain 230-configuration stencil space, the LBM
+space, the 10^6-configuration stress batch), plain against batched, and the
+continuous-batching server on the seeded Poisson trace at several arrival
+rates.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--mode batched|plain]
 """
@@ -21,10 +25,13 @@ sys.path.insert(0, ROOT)
 
 # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz: int32 VALU lane-operations per second
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# irreducible integer lane-ops of one (thread, instruction) address evaluation:
-# 64-bit index add and scale (4), sector and line shifts (2), key offsets (2),
-# entry packing (2)
-OPS_PER_EVAL = 10
+# integer lane-ops charged per (thread, instruction) address evaluation: about
+# 10 for the address and key (64-bit index add and scale, sector and line
+# shifts, key offsets, entry packing) and about 20 for the wavefront and LDS
+# deduplication of the key
+OPS_PER_EVAL = 30
+# the address-and-key part alone (the work no deduplication scheme avoids)
+USEFUL_OPS_PER_EVAL = 10
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_stencil_batched_traffic.md")
@@ -53,16 +60,33 @@ def measured_traffic(workload):
         return None
 
 
+def stress_batch():
+    from paper_2204_14242_amd import workloads as W
+    return W.stress_spaces(seed=5, total=1_000_000)
+
+
+def single(name):
+    def f():
+        from paper_2204_14242_amd import workloads as W
+        return [getattr(W, name)()]
+    return f
+
+
+# name -> list of (kernel, hw, space) estimated together in one call
+WORKLOADS = {"stencil_batched": single("stencil_batched"), "stencil_plain": single("stencil_plain"),
+             "lbm_batched": single("lbm_batched"), "layer_condition_scan": single("layer_condition_scan"),
+             "stress": stress_batch}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1)
     p.add_argument("--warmup", type=int, default=0)
     p.add_argument("--mode", choices=["batched", "plain"], default="batched")
-    p.add_argument("--workload", choices=["stencil_batched", "stencil_plain", "lbm_batched"],
-                   default="stencil_batched")
+    p.add_argument("--workload", choices=list(WORKLOADS), default="stencil_batched")
     p.add_argument("--arena-gib", type=float, default=96.0)
-    p.add_argument("--cpu-budget-s", type=float, default=20.0)
+    p.add_argument("--cpu-budget-s", type=float, default=24.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--plain-sample", type=int, default=192,
                    help="configurations of the workload estimated in plain and batched form side by side")
@@ -71,8 +95,15 @@ def parse():
                         "size for scaling HBM byte counters)")
     p.add_argument("--no-row-ranges", dest="row_ranges", action="store_false",
                    help="skip the leg that repeats the workload with per-row address ranges")
-    p.add_argument("--serve-requests", type=int, default=24,
-                   help="requests of the seeded Poisson trace replayed through the server (0 = skip)")
+    p.add_argument("--no-other-workloads", dest="other_workloads", action="store_false",
+                   help="skip the timed estimates of the other workloads")
+    p.add_argument("--serve-requests", type=int, default=100,
+                   help="requests of the seeded Poisson trace replayed through the server per arrival "
+                        "rate (0 = skip)")
+    p.add_argument("--serve-fractions", default="0.3,0.6,0.9",
+                   help="arrival rates of the served sweep, as fractions of the served capacity")
+    p.add_argument("--autotune-sample", type=int, default=0,
+                   help="configurations of the workload the autotuner times (0 = hand-set defaults)")
     return p.parse_args()
 
 
@@ -126,12 +157,13 @@ def plain_vs_batched(ctx, kid, hid, space, n, sample):
             "batched_over_plain": rates["batched"] / rates["plain"], "identical": True}
 
 
-def served(ctx, n_requests, configs_per_s=None):
+def served(ctx, n_requests, offered_configs_per_s=None):
     """Replay the first requests of the seeded Poisson trace (200 requests/s,
     sizes log-uniform 10..50,000, three kernel families, three HW sets)
-    through the continuous-batching server, open loop.  With configs_per_s,
-    the arrival times are stretched so that the trace offers that many
-    configurations per second instead."""
+    through the continuous-batching server, open loop.  With
+    offered_configs_per_s, the arrival times are stretched so that the trace
+    offers that many configurations per second instead.  Latency = completion
+    - scheduled arrival."""
     import numpy as np
     from paper_2204_14242_amd import workloads as W
     from paper_2204_14242_amd import wsest
@@ -145,16 +177,16 @@ def served(ctx, n_requests, configs_per_s=None):
     reqs = W.serving_requests(sizes, seed=4, n_requests=n_requests, rate=200.0)
     total = sum(len(r["explicit"]) for r in reqs)
     scale = 1.0
-    if configs_per_s:
-        scale = (total / configs_per_s) / max(reqs[-1]["t_arrival"], 1e-9)
+    if offered_configs_per_s:
+        scale = (total / offered_configs_per_s) / max(reqs[-1]["t_arrival"], 1e-9)
         for r in reqs:
             r["t_arrival"] *= scale
     srv = wsest.Server(ctx, memory_budget_bytes=8 << 30, max_inflight=8)
     tickets = []
     try:
-        t0 = time.perf_counter()
+        t0 = time.perf_counter_ns()    # CLOCK_MONOTONIC, the server's clock
         for r in reqs:
-            delay = t0 + r["t_arrival"] - time.perf_counter()
+            delay = (t0 + r["t_arrival"] * 1e9 - time.perf_counter_ns()) / 1e9
             if delay > 0:
                 time.sleep(delay)
             f = r["family"]
@@ -163,74 +195,167 @@ def served(ctx, n_requests, configs_per_s=None):
         for i, t in enumerate(tickets):
             if not srv.wait(t, timeout_us=600_000_000):
                 raise SystemExit(f"served request {i} did not finish")
-            print(f"served request {i} done ({len(reqs[i]['explicit'])} configurations)",
-                  file=sys.stderr, flush=True)
         times = [srv.times(t) for t in tickets]
     finally:
         srv.stop()
-    lat_ms = np.array([(d - s) / 1e6 for s, _, d in times])
-    span_s = (max(d for _, _, d in times) - min(s for s, _, _ in times)) / 1e9
-    out = {"requests": len(reqs), "configs": total, "configs_per_s": total / span_s,
-           "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99))}
-    if configs_per_s:
-        out["offered_configs_per_s"] = configs_per_s
-        out["offered_requests_per_s"] = 200.0 / scale
-        out["trace"] = ("the same requests with arrival times stretched so the trace offers 0.7x the measured "
-                        "served capacity; latency = completion - arrival")
-    else:
-        out["trace"] = ("first requests of the seed-4 Poisson trace at 200 requests/s, replayed open loop; "
-                        "offered load exceeds capacity, so latencies include queueing")
+    lat_ms = np.array([(d - (t0 + r["t_arrival"] * 1e9)) / 1e6 for (_, _, d), r in zip(times, reqs)])
+    span_s = (max(d for _, _, d in times) - t0) / 1e9
+    out = {"requests": len(reqs), "latencies": len(lat_ms), "configs": total,
+           "configs_per_s": total / span_s, "requests_per_s": len(reqs) / span_s,
+           "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+           "offered_requests_per_s": 200.0 / scale,
+           "offered_configs_per_s": total / max(reqs[-1]["t_arrival"], 1e-9)}
+    print(f"served {len(reqs)} requests at {out['offered_requests_per_s']:.3g} requests/s: "
+          f"p50 {out['p50_ms']:.0f} ms, p99 {out['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
     return out
 
 
+def served_legs(ctx, n_requests, fractions):
+    """The trace at its own 200 requests/s (offered load far above capacity:
+    latencies are queueing), then at fractions of the capacity measured
+    there.  The server runs with row ranges (exact; byte-identical results),
+    since per-thread evaluation of the trace's 1024^3 stencil requests would
+    hold the GPU for minutes per rate."""
+    base = ctx.tuning()
+    try:
+        ctx.set_tuning(row_ranges=1)
+        backlog = served(ctx, n_requests)
+        sweep = [dict(served(ctx, n_requests, offered_configs_per_s=f * backlog["configs_per_s"]),
+                      capacity_fraction=f) for f in fractions]
+    finally:
+        ctx.set_tuning(**base)
+    return {"tuning": "row_ranges=1, other parameters as the headline",
+            "latency": "completion - scheduled arrival (open loop, seed-4 trace)",
+            "at_200_rps": backlog, "sweep": sweep}
+
+
 def cpu_baseline(kernel, hw, space, per_config_evals, budget_s):
-    """Time the oracle, as it stands, on a seeded sample of the workload's
-    configurations (cheapest-first strata so the sample stays bounded), then
-    scale its measured evaluation rate to configurations per second of the
-    whole workload."""
+    """Time the oracle, as it stands, on a seeded sample of the workload that
+    follows its cost mix: the configurations are cut into cost strata
+    (powers of 4 of their evaluation counts), every stratum the budget
+    affords is sampled, and the oracle's evaluation rate in each stratum is
+    applied to that stratum's share of the workload's evaluations (strata
+    above the largest affordable one take its rate)."""
     import numpy as np
     import oracle
     oracle.build(force=False)
-    n_threads = min(os.cpu_count() or 1, 16)
+    nproc = os.cpu_count() or 1
+    n_threads = min(nproc, 16)          # the host share of one GPU
     rng = np.random.default_rng(2024)
-    cand = np.nonzero(per_config_evals > 0)[0]
-    # configurations costing at most ~1/4 of the budget on one core at 2e7 eval/s
-    cheap = cand[per_config_evals[cand] <= budget_s * 2e7 / 4]
-    order = rng.permutation(cheap)
-    picked, evals, t_used = [], 0, 0.0
-    chunk = max(n_threads, 8)
-    i = 0
-    while i < len(order) and t_used < budget_s:
-        batch = sorted(int(v) for v in order[i:i + chunk])
-        i += chunk
-        sp = dict(space, explicit=batch)
+    ev = per_config_evals
+    ok = np.nonzero(ev > 0)[0]
+    stratum = np.floor(np.log(ev[ok]) / np.log(4.0)).astype(int)
+    # the largest stratum one thread finishes in about a fifth of the budget (2e7 evaluations/s)
+    cap = int(np.floor(np.log(budget_s / 5 * 2e7) / np.log(4.0)))
+    levels = sorted(set(stratum.tolist()))
+    rates, sample, t_all = {}, 0, 0.0
+    per_level_budget = budget_s / max(1, len([lv for lv in levels if lv <= cap]))
+    for lv in levels:
+        if lv > cap:
+            continue
+        members = ok[stratum == lv]
+        pick = rng.permutation(members)
+        t_used, e_used, done = 0.0, 0, 0
+        i = 0
+        while i < len(pick) and t_used < per_level_budget:
+            batch = sorted(int(v) for v in pick[i:i + n_threads])
+            i += n_threads
+            t0 = time.perf_counter()
+            oracle.estimate(kernel, hw, dict(space, explicit=batch), n_threads=n_threads)
+            t_used += time.perf_counter() - t0
+            e_used += int(ev[batch].sum())
+            done += len(batch)
+        rates[lv] = e_used / t_used
+        sample += done
+        t_all += t_used
+    top = max(rates)
+    t_pred = 0.0
+    for lv in levels:
+        e = float(ev[ok[stratum == lv]].sum())
+        t_pred += e / rates[lv if lv in rates else top]
+    n = len(ev)
+    return {"value": n / t_pred, "unit": "configs/s", "cores": n_threads, "nproc": nproc, "kind": "oracle",
+            "sample": f"{sample} seeded configurations in {len(rates)} cost strata (4^k evaluations, "
+                      f"k <= {cap}; {t_all:.1f} s on {n_threads} threads); each stratum's measured "
+                      f"oracle rate applied to its share of the workload's {float(ev.sum()):.3g} "
+                      f"evaluations, strata above k = {cap} at the rate of the largest measured one",
+            "predicted_s_per_step": t_pred}
+
+
+def other_workloads(ctx, dev, skip):
+    """One timed batched estimate of each other workload (after an untimed
+    estimate of a small part of it that also warms the folding expansions and
+    graphs): the plain 230-configuration stencil space on 256^3, the LBM-shaped
+    space, the constant-volume domain-size scan, and the 10^6-configuration
+    stress batch of random affine kernels."""
+    import numpy as np
+    import torch
+    from paper_2204_14242_amd import wsest
+    legs = {}
+    stream = torch.cuda.current_stream().cuda_stream
+    for name in ("stencil_plain", "lbm_batched", "layer_condition_scan", "stress"):
+        if name == skip:
+            continue
+        items = WORKLOADS[name]()
+        specs = []
+        for k, hw, sp in items:
+            specs.append((ctx.register_kernel(k), ctx.register_hw(hw), sp))
+        n = sum(ctx.space_size(*s) for s in specs)
+        out = torch.empty(n * wsest.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        rank = torch.empty(n, dtype=torch.int32, device=dev)
+        warm = specs[:8] if len(specs) > 1 else [(specs[0][0], specs[0][1],
+                                                  dict(specs[0][2], explicit=list(range(0, n, 37))))]
+        ctx.estimate(warm, mode=wsest.BATCHED)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        oracle.estimate(kernel, hw, sp, n_threads=n_threads)
-        t_used += time.perf_counter() - t0
-        picked += batch
-        evals += int(per_config_evals[batch].sum())
-    rate = evals / t_used                       # evaluations per second
-    total = float(per_config_evals.sum())
-    cfg_per_s = len(per_config_evals) / (total / rate)
-    # one core: the sample's cheapest configurations again, one at a time, single-threaded, for
-    # about a quarter of the budget
-    ev1, t1, n1 = 0, 0.0, 0
-    for v in sorted(picked, key=lambda v: per_config_evals[v]):
-        if t1 >= budget_s / 4:
-            break
-        t0 = time.perf_counter()
-        oracle.estimate(kernel, hw, dict(space, explicit=[v]), n_threads=1)
-        t1 += time.perf_counter() - t0
-        ev1 += int(per_config_evals[v])
-        n1 += 1
-    rate1 = ev1 / t1 if t1 > 0 else 0.0
-    return {"value": cfg_per_s, "unit": "configs/s", "cores": n_threads, "kind": "oracle",
-            "value_1core": len(per_config_evals) / (total / rate1) if rate1 > 0 else None,
-            "sample": f"{len(picked)} seeded random configurations of the workload costing at "
-                      f"most {budget_s * 2e7 / 4:.2g} evaluations each ({evals:.3g} evaluations, "
-                      f"{t_used:.1f} s); the oracle's {rate:.3g} evaluations/s scaled to the "
-                      f"workload's {total:.3g} evaluations; value_1core: {n1} of them on one thread "
-                      f"({ev1:.3g} evaluations, {t1:.1f} s, {rate1:.3g} evaluations/s)"}
+        ctx.estimate(specs, mode=wsest.BATCHED, out=out, rank=rank, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.last_stats()
+        tm = ctx.last_timings()
+        res = np.frombuffer(out.cpu().numpy().tobytes(), dtype=wsest.RESULT_DTYPE)
+        phase = OPS_PER_EVAL * st["evals"] / (tm[1] / 1e3) / 1e12 if tm[1] > 0 else 0.0
+        legs[name] = {"configs": n, "configs_ok": int((res["status"] == 0).sum()), "spaces": len(specs),
+                      "configs_per_s": n / dt, "ms": dt * 1e3, "evaluations": st["evals"],
+                      "arena_rounds": st["rounds"], "evaluation_ms": tm[1],
+                      "evaluation_phase_frac": phase / VALU_PEAK_TOPS}
+        print(f"workload {name}: {n} configurations in {dt * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        del out, rank
+    return legs
+
+
+def tuning_cache_path():
+    return os.environ.get("WSE_TUNING_CACHE", os.path.join(os.path.expanduser("~"), ".cache",
+                                                           "wsest_tuning.json"))
+
+
+def choose_tuning(ctx, specs, workload, sample):
+    """Autotuner's choice for this device and space class, cached as JSON."""
+    import hashlib
+    import torch
+    from paper_2204_14242_amd import wsest
+    lib_hash = hashlib.sha256(open(wsest.LIB_PATH, "rb").read()).hexdigest()[:16]
+    key = f"{torch.cuda.get_device_name(0)}|{workload}|{lib_hash}"
+    path = tuning_cache_path()
+    cache = {}
+    if os.path.exists(path):
+        try:
+            cache = json.load(open(path))
+        except (OSError, ValueError):
+            cache = {}
+    if key in cache:
+        ctx.set_tuning(**cache[key])
+        return {"source": "cache", "tuning": cache[key], "cache": path}
+    t0 = time.perf_counter()
+    chosen = ctx.autotune(specs, sample=sample)
+    cache[key] = chosen
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        json.dump(cache, open(path, "w"), indent=1)
+    except OSError:
+        pass
+    print(f"autotuned in {time.perf_counter() - t0:.1f} s: {chosen}", file=sys.stderr, flush=True)
+    return {"source": f"autotune on {sample} configurations", "tuning": chosen, "cache": path}
 
 
 def main():
@@ -248,18 +373,22 @@ def main():
     from paper_2204_14242_amd import workloads as W
     from paper_2204_14242_amd import wsest
 
-    kernel, hw, space = getattr(W, a.workload)()
+    items = WORKLOADS[a.workload]()
+    kernel, hw, space = items[0]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ctx = wsest.Context(0, arena_bytes=int(a.arena_gib * (1 << 30)))
-    kid = ctx.register_kernel(kernel)
-    hid = ctx.register_hw(hw)
-    n = ctx.space_size(kid, hid, space)
+    specs = [(ctx.register_kernel(k), ctx.register_hw(h), sp) for k, h, sp in items]
+    kid, hid = specs[0][0], specs[0][1]
+    n = sum(ctx.space_size(*s) for s in specs)
     out = torch.empty(n * wsest.RESULT_DTYPE.itemsize, dtype=torch.uint8, device=dev)
     rank = torch.empty(n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream().cuda_stream
     mode = wsest.BATCHED if a.mode == "batched" else wsest.PLAIN
-    specs = [(kid, hid, space)]
+    if a.autotune_sample > 0:
+        tuning = choose_tuning(ctx, specs, a.workload, a.autotune_sample)
+    else:
+        tuning = {"source": "defaults (hand-swept on this workload)", "tuning": ctx.tuning()}
     if a.copy_calibration_gib > 0:
         nbytes = int(a.copy_calibration_gib * (1 << 30))
         src = torch.ones(nbytes, dtype=torch.uint8, device=dev)
@@ -298,14 +427,12 @@ def main():
     phase = OPS_PER_EVAL * evals / (eval_ms / 1e3) / 1e12 if eval_ms > 0 else 0.0
     if dl_launches > 0 and dl_ms > 0:
         kname = "k_eval<true> (wave and layer passes of lattice kernels on bitmaps)"
-        achieved = OPS_PER_EVAL * dl_evals / (dl_ms / 1e3) / 1e12
-        avg_ms = dl_ms / dl_launches
-        per_launch = OPS_PER_EVAL * dl_evals / dl_launches
+        k_evals, k_ms, k_launches = dl_evals, dl_ms, dl_launches
     else:
         kname = "k_eval (all evaluation launches of a round)"
-        achieved = phase
-        avg_ms = eval_ms / max(st["rounds"] * a.steps, 1)
-        per_launch = OPS_PER_EVAL * evals / max(st["rounds"] * a.steps, 1)
+        k_evals, k_ms, k_launches = evals, eval_ms, max(st["rounds"] * a.steps, 1)
+    achieved = OPS_PER_EVAL * k_evals / (k_ms / 1e3) / 1e12
+    useful = USEFUL_OPS_PER_EVAL * k_evals / (k_ms / 1e3) / 1e12
     line = {
         "metric": "configs estimated/sec (batched)" if mode == wsest.BATCHED else "configs estimated/sec (plain)",
         "value": n * a.steps / dt,
@@ -321,24 +448,29 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "configs": n, "configs_ok": n_ok, "mode": a.mode,
                    "evaluations_per_step": st["evals"], "table_bytes_per_step": st["table_bytes"],
-                   "eval_launches_per_step": st["eval_launches"], "arena_rounds": st["rounds"]},
+                   "eval_launches_per_step": st["eval_launches"], "arena_rounds": st["rounds"],
+                   "tuning": tuning},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(a.workload),
-                     "kernel": kname, "avg_launch_ms": avg_ms, "lane_ops_per_launch": per_launch,
+                     "kernel": kname, "avg_launch_ms": k_ms / k_launches,
+                     "lane_ops_per_launch": OPS_PER_EVAL * k_evals / k_launches,
+                     "evaluations_per_launch": k_evals / k_launches,
                      "ops_per_eval": OPS_PER_EVAL,
+                     "frac_address_and_key_only": useful / VALU_PEAK_TOPS,
                      "evaluation_phase": {"achieved": phase, "frac": phase / VALU_PEAK_TOPS,
                                           "ms_per_step": eval_ms / a.steps}},
     }
     if a.row_ranges:
         line["row_ranges"] = row_ranges_leg(ctx, specs, mode, out, rank, stream, n)
-    if a.plain_sample > 0:
+    del out, rank
+    if a.plain_sample > 0 and len(specs) == 1:
         line["plain_vs_batched"] = plain_vs_batched(ctx, kid, hid, space, n, a.plain_sample)
+    if a.other_workloads:
+        line["workloads"] = other_workloads(ctx, dev, skip=a.workload)
     if a.serve_requests > 0:
-        line["served"] = served(ctx, a.serve_requests)
-        # the rate at which latency stays bounded: 0.7x the capacity just measured
-        line["served_sustainable"] = served(ctx, a.serve_requests,
-                                            configs_per_s=0.7 * line["served"]["configs_per_s"])
-    if not a.no_cpu_baseline:
+        fr = [float(v) for v in a.serve_fractions.split(",") if v]
+        line["served"] = served_legs(ctx, a.serve_requests, fr)
+    if not a.no_cpu_baseline and len(specs) == 1:
         line["cpu_baseline"] = cpu_baseline(kernel, hw, space, per_config_evals, a.cpu_budget_s)
     print(json.dumps(line), flush=True)
     ctx.close()

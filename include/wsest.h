@@ -68,7 +68,9 @@ const char* wse_last_error(const wse_ctx* ctx);
 typedef struct {
     int32_t elem_bytes;   /* element size in bytes, > 0 */
     int32_t pad;
-    int64_t align_bytes;  /* byte address of element 0 */
+    int64_t align_bytes;  /* byte address of element 0, in [-2^62, 2^62) (else WSE_ERANGE at
+                             registration); a configuration that evaluates an address outside
+                             that range gets status WSE_ERANGE */
 } wse_field;
 
 /* Raw affine address expression (Sec. 1.2): the element index of one load
@@ -96,6 +98,19 @@ typedef struct {
 #define WSE_KERNEL_LATTICE 0
 #define WSE_KERNEL_AFFINE 1
 
+/* Address spaces of the wave and layer sets (the DRAM-level footprints).
+ * WSE_ADDR_LINEAR: linear byte addresses, field base = alignment (Sec. 4.3).
+ * WSE_ADDR_MULTIDIM (lattice kernels only; Sec. 4.4.1, the optional
+ * multi-dimensional address space): a point of a field names the tuple
+ * (field, z, y, floor(x * elem / unit)) of its array coordinates, so two
+ * accesses are distinct when any coordinate differs (no wrap-around from
+ * one row into the next), a row never shares a sector or line with another
+ * row, and the alignment plays no part.  The block pass (L1 cycles and
+ * L2->L1 volumes) keeps linear addresses.  Needs one element size per
+ * configuration (else that configuration's status is WSE_EINVAL). */
+#define WSE_ADDR_LINEAR 0
+#define WSE_ADDR_MULTIDIM 1
+
 typedef struct {
     int32_t kind;             /* WSE_KERNEL_LATTICE or WSE_KERNEL_AFFINE */
     int32_t n_fields;         /* 1 .. 65535 */
@@ -104,6 +119,8 @@ typedef struct {
     const wse_field* fields;  /* [n_fields] */
     const void* items;        /* wse_access[n_items] or wse_expr[n_items] */
     double flops_per_lup;     /* floating-point ops per lattice update; 0 = FP limiter off */
+    int32_t address_space;    /* WSE_ADDR_LINEAR (0) or WSE_ADDR_MULTIDIM */
+    int32_t pad;              /* 0 */
 } wse_kernel_desc;
 
 /* Register a kernel; its tables are copied to the device and stay resident
@@ -171,7 +188,19 @@ wse_status wse_space_size(wse_ctx* ctx, const wse_space* space, int64_t* n_confi
 /* Per-configuration result.  Counts are exact; volumes are in sectors
  * (multiply by sector_bytes for bytes).  Suffix B = representative (centre)
  * thread block, W = middle wave of co-resident blocks, L = layer sets.
- * s_layer[d] = first block of the layer set of dimension d, -1 if empty. */
+ * s_layer[d] = first block of the layer set of dimension d, -1 if empty.
+ * Where each term comes from in the paper:
+ *   l1_cycles_B (bank conflicts per half-warp instruction): Sec. 4.2,
+ *     "L1 Cache Load Throughput";
+ *   up_ld_B, up_st_B, comp_ld_B, lines_ld_B and v_l2l1_ld: Sec. 4.3,
+ *     "L2 to L1 Cache Transfers" (upper limit, compulsory volume, allocation);
+ *   fpld_W, comp_st_W, up_st_W, lines_W: Sec. 4.4, "DRAM - L2 Cache Data
+ *     Transfer Volumes" (wave footprint, redundant stores);
+ *   s_layer, lines_L, shell: Sec. 4.4.2, "Warm Cache Reuse" (layer sets);
+ *   O_*, R_* (R(O) = a exp(-b exp(c O)) per fit), v_dram_ld, v_dram_st:
+ *     Sec. 4.5, "Capacity Misses";
+ *   bpl_*, p_l1, p_l2, p_dram, p_fp, perf, limiter (the lowest of four
+ *     limiters): Sec. 2, "Performance Model", with Sec. 4.1 for p_fp. */
 typedef struct {
     int32_t status, limiter;     /* limiter 0 L1, 1 L2, 2 DRAM, 3 FP; -1 on error */
     int32_t shape[3], fold[3], domain[3], elem;   /* domain = grid for affine */
@@ -187,10 +216,19 @@ typedef struct {
 #define WSE_BATCHED 1  /* all configurations of all spaces in arena rounds; each round is one
                           replay of a captured HIP graph of resident-loop kernels */
 
-/* Estimate every configuration of n_spaces spaces.  out[] receives the
+/* Estimate every configuration of n_spaces spaces: the counting of
+ * Sec. 4.2-4.4 and the capacity model of Sec. 4.5 per configuration, the
+ * four-limiter estimate of Sec. 2, and the ranking by predicted performance
+ * that Sec. 5.8 ("Performance Prediction") evaluates.  out[] receives the
  * results of space 0, then space 1, ...; rank_out[] (optional) the 0-based
  * rank of each configuration within its space (perf descending, canonical
- * index ascending).  out_capacity = entries available in out/rank_out.
+ * index ascending).  out_capacity = entries available in out/rank_out;
+ * WSE_EINVAL if smaller than the configurations, or for an invalid space
+ * (unknown ids, empty shape set, explicit index outside the space or
+ * repeated).  Per-configuration problems (folding that does not divide the
+ * domain, a block larger than the CU holds: WSE_EINVAL; an address beyond
+ * +-2^62 or keys that do not pack: WSE_ERANGE; tables larger than the arena:
+ * WSE_ENOMEM) are reported in that result's status only.
  * Returns after the results are written (the stream is synchronised). */
 wse_status wse_estimate(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces,
                         wse_result* out, int32_t* rank_out, int64_t out_capacity,
@@ -238,18 +276,23 @@ wse_status wse_autotune(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces,
 
 /* A server estimates requests in the background with continuous batching:
  * every admitted request is decoded on the device at once, and each arena
- * round of the evaluation kernels packs the pending configurations of all
- * admitted requests, oldest first, so that a request arriving while others
- * run shares their rounds instead of waiting for them to finish.  Requests
- * are admitted while the device memory of all requests in flight stays
- * within memory_budget_bytes and at most max_inflight are in flight; the
- * rest wait in a FIFO queue.  The results of a request do not depend on
- * what else is in flight (every configuration owns its tables and
- * counters). */
+ * round of the evaluation kernels takes pending configurations of all
+ * admitted requests in turn (one of each, oldest request first, until the
+ * round's tables fill the arena or its estimated cost reaches round_evals
+ * address evaluations), so that a request arriving while others run joins
+ * the next short round instead of waiting for them to finish.  Requests are
+ * admitted while the device records (configuration, counter and result
+ * records) of all requests in flight stay within memory_budget_bytes and
+ * at most max_inflight are in flight; the rest wait in a FIFO queue.  The
+ * evaluation tables are not part of that budget: they live in the
+ * context's arena, whose rounds every request shares.  The results of a
+ * request do not depend on what else is in flight (every configuration
+ * owns its tables and counters). */
 typedef struct {
     size_t memory_budget_bytes;  /* device memory for requests in flight (0 = 8 GiB) */
     int32_t max_inflight;        /* requests in flight at once (0 = 64) */
     int32_t max_queue;           /* queued requests before wse_submit says WSE_EBUSY (0 = 1000000) */
+    int64_t round_evals;         /* estimated address evaluations per serving round (0 = 2^37) */
 } wse_server_opts;
 
 /* Start the server thread of a context (one per context). */
@@ -289,12 +332,14 @@ wse_status wse_rhat(wse_ctx* ctx, const wse_fit* fit, const double* O, double* R
  * on their own stream).  `n` entries (<= 8) are copied. */
 wse_status wse_last_timings(const wse_ctx* ctx, double* ms, int32_t n);
 
-/* Work statistics of the last wse_estimate call on this context (n <= 8
+/* Work statistics of the last wse_estimate call on this context (n <= 9
  * entries): [0] (thread, instruction) address evaluations performed over all
  * thread sets, [1] table bytes used (hash tables and bitmaps), [2]
  * evaluation-kernel launches, [3] arena rounds, [4] configurations
  * evaluated, [5] configurations with sets kept as bitmaps, [6] evaluations
- * performed by the lattice bitmap launches, [7] their number. */
+ * performed by the lattice bitmap launches, [7] their number, [8] thread
+ * rows whose wave and layer sets were filled by row ranges (0 unless the
+ * tuning's row_ranges is 1). */
 wse_status wse_last_stats(wse_ctx* ctx, int64_t* stats, int32_t n);
 
 /* Address evaluations the last wse_estimate call performed for each of its

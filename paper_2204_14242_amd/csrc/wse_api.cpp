@@ -55,13 +55,18 @@ static int64_t now_ns()
 
 namespace {
 
+// A device buffer that grows by reallocation, or a borrowed piece of memory
+// the library does not own, which
+// never grows and is never freed.
 template <typename T>
 struct DevBuf {
     T* p = nullptr;
     size_t cap = 0;  // elements
+    bool owned = true;
     hipError_t reserve(size_t n)
     {
         if (n <= cap) return hipSuccess;
+        if (!owned) return hipErrorOutOfMemory;
         size_t want = std::max<size_t>(n, cap * 2);
         if (p) (void)hipFree(p);
         p = nullptr;
@@ -70,11 +75,19 @@ struct DevBuf {
         if (e == hipSuccess) cap = want;
         return e;
     }
+    void borrow(T* q, size_t n)
+    {
+        release();
+        p = q;
+        cap = n;
+        owned = false;
+    }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
         p = nullptr;
         cap = 0;
+        owned = true;
     }
 };
 
@@ -168,6 +181,7 @@ struct Job {
     DevBuf<Cfg> d_cfgs;
     DevBuf<Counters> d_ctr;
     DevBuf<Result> d_res;
+    const Expansion* exp_tab = nullptr;  // expansions of this request's own (no-allocation path)
     std::vector<Cfg> cfgs;          // host copy of the decoded configurations
     std::vector<int64_t> runnable;  // configurations that go through the evaluation kernels
     size_t next = 0;                // first runnable configuration not yet in a round
@@ -195,6 +209,10 @@ struct Job {
     }
 };
 
+// resident registries have fixed device capacities, so that uploading a new
+// entry never moves a table that a running round reads
+constexpr size_t kMaxKernels = 4096, kMaxHws = 4096;
+
 struct wse_ctx {
     int device = 0;
     char* arena = nullptr;
@@ -219,6 +237,7 @@ struct wse_ctx {
     hipEvent_t dl_t0 = nullptr, dl_t1 = nullptr;  // around the lattice bitmap launch (timing)
     double last_dl_ms = 0;        // lattice bitmap launches of the last call: time, launches
     int64_t last_dl_launches = 0;
+    int64_t last_row_units = 0;   // thread rows whose sets the last call filled by row ranges
     // captured round graphs: [0] clear + evaluation launches, [1] counting
     // round graphs: clear, general evaluation launches, lattice bitmap launch, count
     enum { G_FILL = 0, G_GEN = 1, G_DL = 2, G_COUNT = 3, N_GRAPHS = 4 };
@@ -299,6 +318,15 @@ wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out)
         delete c;
         return fail(WSE_ENOMEM, std::string("arena allocation failed: ") + hipGetErrorString(e));
     }
+    e = c->d_kernels.reserve(kMaxKernels);
+    if (e == hipSuccess) e = c->d_hws.reserve(kMaxHws);
+    if (e != hipSuccess) {
+        c->d_kernels.release();
+        c->d_hws.release();
+        (void)hipFree(c->arena);
+        delete c;
+        return fail(WSE_EDEVICE, std::string("context set-up: ") + hipGetErrorString(e));
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
         c->n_cu = prop.multiProcessorCount;
@@ -319,6 +347,8 @@ wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out)
         if (c->fork) (void)hipEventDestroy(c->fork);
         if (c->rs2) (void)hipStreamDestroy(c->rs2);
         if (c->rs) (void)hipStreamDestroy(c->rs);
+        c->d_kernels.release();
+        c->d_hws.release();
         (void)hipFree(c->arena);
         delete c;
         return fail(WSE_EDEVICE, std::string("round streams: ") + hipGetErrorString(e));
@@ -375,14 +405,21 @@ wse_status wse_kernel_register(wse_ctx* c, const wse_kernel_desc* d, int32_t* ke
         return fail(WSE_EINVAL, "kernel needs 1..65535 fields and items");
     if (d->ghost < 0 || d->ghost > (1 << 20)) return fail(WSE_EINVAL, "ghost width out of range");
     if (!(d->flops_per_lup >= 0.0)) return fail(WSE_EINVAL, "flops_per_lup must be >= 0");
+    if (d->address_space != WSE_ADDR_LINEAR && d->address_space != WSE_ADDR_MULTIDIM)
+        return fail(WSE_EINVAL, "unknown address space");
+    if (d->address_space == WSE_ADDR_MULTIDIM && d->kind != WSE_KERNEL_LATTICE)
+        return fail(WSE_EINVAL, "the multi-dimensional address space is for lattice kernels");
+    if (c->kernels.size() >= kMaxKernels) return fail(WSE_ENOMEM, "a context holds at most 4096 kernels");
     std::vector<int32_t> elem(d->n_fields);
     std::vector<int64_t> align(d->n_fields);
     int32_t uni = d->fields[0].elem_bytes;
     for (int f = 0; f < d->n_fields; f++) {
         if (d->fields[f].elem_bytes <= 0 || d->fields[f].elem_bytes > (1 << 20))
             return fail(WSE_EINVAL, "field element size must be in 1..2^20");
-        if (d->fields[f].align_bytes < -((int64_t)1 << 60) || d->fields[f].align_bytes > ((int64_t)1 << 60))
-            return fail(WSE_ERANGE, "field alignment out of range");
+        // addresses are representable in [-2^62, 2^62); each configuration's
+        // evaluated addresses are checked against that range when it is decoded
+        if (d->fields[f].align_bytes < -((int64_t)1 << 62) || d->fields[f].align_bytes >= ((int64_t)1 << 62))
+            return fail(WSE_ERANGE, "field alignment outside [-2^62, 2^62)");
         elem[f] = d->fields[f].elem_bytes;
         align[f] = d->fields[f].align_bytes;
         if (elem[f] != uni) uni = 0;
@@ -395,6 +432,7 @@ wse_status wse_kernel_register(wse_ctx* c, const wse_kernel_desc* d, int32_t* ke
     k.dev.ghost = d->ghost;
     k.dev.flops_per_lup = d->flops_per_lup;
     k.dev.uniform_elem = uni;
+    k.dev.multidim = d->address_space == WSE_ADDR_MULTIDIM;
     size_t item_bytes;
     std::vector<AccessL> acc;
     std::vector<ExprA> ex;
@@ -473,6 +511,7 @@ wse_status wse_hw_register(wse_ctx* c, const wse_hw* h, int32_t* hw_id)
             return fail(WSE_EINVAL, "fit needs 0 <= a <= 1, b >= 0, c >= 0");
     if (!(h->clock_hz > 0 && h->bw_l2 > 0 && h->bw_dram > 0 && h->flops_peak >= 0))
         return fail(WSE_EINVAL, "clock and bandwidths must be positive");
+    if (c->hws.size() >= kMaxHws) return fail(WSE_ENOMEM, "a context holds at most 4096 hardware sets");
     HwDev d;
     std::memset(&d, 0, sizeof(d));
     d.line_bytes = h->line_bytes;
@@ -619,15 +658,32 @@ static wse_status sync_tables(wse_ctx* c, hipStream_t st)
     return WSE_OK;
 }
 
-static DevTables dev_tables(wse_ctx* c, const SpaceDev* spaces, int n_spaces)
+static DevTables dev_tables(wse_ctx* c, const SpaceDev* spaces, int n_spaces,
+                            const Expansion* expansions = nullptr)
 {
     DevTables t;
     t.kernels = c->d_kernels.p;
     t.hws = c->d_hws.p;
-    t.expansions = c->d_exp.p;
+    t.expansions = expansions ? expansions : c->d_exp.p;
     t.spaces = spaces;
     t.n_spaces = n_spaces;
     return t;
+}
+
+// Device memory one sequence of arena rounds runs in: the context's arena,
+// work list and round descriptor, or pieces of memory lent to one call.
+struct RoundMem {
+    char* arena;
+    size_t arena_bytes;
+    DevBuf<WorkEntry>* work;       // grows only if owned
+    RoundDesc* rd;
+    const Expansion* expansions;   // null: the context's resident expansions
+    size_t max_configs;            // configurations per round (work list bound)
+};
+
+static RoundMem ctx_round_mem(wse_ctx* c)
+{
+    return RoundMem{c->arena, c->arena_bytes, &c->d_work, nullptr, nullptr, SIZE_MAX};
 }
 
 // make sure every (kernel, fy, fz) folding expansion a space needs is resident
@@ -721,10 +777,10 @@ static wse_status job_init(wse_ctx* c, Job& j, const wse_space* spaces, int32_t 
 }
 
 // upload the spaces, decode every configuration on the device, read the plan back
-static wse_status job_prepare(wse_ctx* c, Job& j, hipStream_t st)
+static wse_status job_prepare(wse_ctx* c, Job& j, hipStream_t st, size_t arena_bytes)
 {
     WSE_TRY(sync_tables(c, st));
-    WSE_TRY(ensure_expansions(c, j.sp, st));
+    if (!j.exp_tab) WSE_TRY(ensure_expansions(c, j.sp, st));
     const int n_spaces = (int)j.sp.size();
     std::vector<int32_t> shapes, outer;
     std::vector<int64_t> expl;
@@ -766,8 +822,8 @@ static wse_status job_prepare(wse_ctx* c, Job& j, hipStream_t st)
     HIP_TRY(j.d_space_first.reserve(n_spaces + 1));
     HIP_TRY(hipMemcpyAsync(j.d_space_first.p, first.data(), first.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(j.d_cfg_space.p, cfg_space.data(), j.total * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    HIP_TRY(launch_decode(j.d_cfgs.p, j.total, dev_tables(c, j.d_spaces.p, n_spaces), c->table_slack,
-                          c->bitmap_log2, st));
+    HIP_TRY(launch_decode(j.d_cfgs.p, j.total, dev_tables(c, j.d_spaces.p, n_spaces, j.exp_tab),
+                          c->table_slack, c->bitmap_log2, st));
     HIP_TRY(launch_fill_zero(j.d_ctr.p, j.total * (int64_t)sizeof(Counters), st));
     j.cfgs.resize(j.total);
     HIP_TRY(hipMemcpyAsync(j.cfgs.data(), j.d_cfgs.p, j.total * sizeof(Cfg), hipMemcpyDeviceToHost, st));
@@ -777,7 +833,7 @@ static wse_status job_prepare(wse_ctx* c, Job& j, hipStream_t st)
     j.runnable.clear();
     for (int64_t i = 0; i < j.total; i++) {
         if (j.cfgs[i].status != 0) continue;
-        if (j.cfgs[i].table_bytes > (int64_t)c->arena_bytes) {
+        if (j.cfgs[i].table_bytes > (int64_t)arena_bytes) {
             j.cfgs[i].status = WSE_ENOMEM;
             HIP_TRY(hipMemcpyAsync(&j.d_cfgs.p[i].status, &j.cfgs[i].status, sizeof(int32_t),
                                    hipMemcpyHostToDevice, st));
@@ -796,7 +852,7 @@ static wse_status job_prepare(wse_ctx* c, Job& j, hipStream_t st)
 static wse_status job_finish(wse_ctx* c, Job& j, hipStream_t st)
 {
     const int n_spaces = (int)j.sp.size();
-    DevTables t = dev_tables(c, j.d_spaces.p, n_spaces);
+    DevTables t = dev_tables(c, j.d_spaces.p, n_spaces, j.exp_tab);
     bool out_dev = is_device_ptr(j.out);
     Result* res = out_dev ? (Result*)j.out : j.d_res.p;
     HIP_TRY(launch_reduce(j.d_cfgs.p, j.d_ctr.p, j.total, t, res, st));
@@ -816,23 +872,45 @@ struct RoundItem {
     int64_t id;
 };
 
-// Take the next configurations of the given requests, oldest request first,
-// while their tables fit the arena together (continuous batching: one round
-// may finish one request and start the next); at most `limit` of them.
-static void form_round(wse_ctx* c, const std::vector<Job*>& jobs, std::vector<RoundItem>& round, size_t limit)
+// Rough device cost of a configuration in address evaluations, for sizing
+// serving rounds: every (thread, instruction) pair of its passes, or, where
+// row ranges fill the wave and layer sets, a few evaluations per thread row
+// and instruction.
+static int64_t config_cost(const wse_ctx* c, const Cfg& g)
+{
+    const bool rows = c->row_ranges && g.kind == 0 && (g.dense & 2) != 0 && g.row_ok;
+    if (!rows) return g.evals[PASS_B] + g.evals[PASS_W] + g.evals[PASS_L];
+    return g.evals[PASS_B] + 4 * (g.w_rows + (g.smin >= 0 ? g.l_rows : 0)) * std::max(1, g.E);
+}
+
+// Take the next configurations of the given requests while their tables fit
+// the arena together and their cost stays within `eval_budget` (the first
+// configuration of a round is always taken): one configuration of each
+// request in turn, oldest request first, so that a request admitted behind a
+// large one shares the next round instead of waiting for the large one to
+// be scheduled (continuous batching); at most `limit` of them.
+static void form_round(const wse_ctx* c, const RoundMem& m, const std::vector<Job*>& jobs,
+                       std::vector<RoundItem>& round, size_t limit, int64_t eval_budget = INT64_MAX)
 {
     round.clear();
-    int64_t used = 0;
-    for (Job* j : jobs) {
-        while (j->next < j->runnable.size() && round.size() < limit) {
+    int64_t used = 0, cost = 0;
+    limit = std::min(limit, m.max_configs);
+    bool more = true;
+    while (more && round.size() < limit) {
+        more = false;
+        for (Job* j : jobs) {
+            if (j->next >= j->runnable.size()) continue;
             int64_t id = j->runnable[j->next];
             int64_t b = j->cfgs[id].table_bytes;
-            if (!round.empty() && used + b > (int64_t)c->arena_bytes) return;
+            int64_t e = config_cost(c, j->cfgs[id]);
+            if (!round.empty() && (used + b > (int64_t)m.arena_bytes || cost + e > eval_budget)) return;
             used += b;
+            cost += e;
             round.push_back({j, id});
             j->next++;
+            more = true;
+            if (round.size() >= limit) return;
         }
-        if (round.size() >= limit) return;
     }
 }
 
@@ -845,18 +923,20 @@ static void form_round(wse_ctx* c, const std::vector<Job*>& jobs, std::vector<Ro
 // the general launches write, and the block passes (few, long work items)
 // leave most of the device to them.  Each piece is one captured graph when
 // `use_graph`, else launched directly (skipping empty lists).
-static hipError_t launch_round(wse_ctx* c, DevTables t, int64_t groups, bool use_graph, const int32_t* counts)
+static hipError_t launch_round(wse_ctx* c, const RoundMem& m, DevTables t, int64_t groups, bool use_graph,
+                               const int32_t* counts)
 {
     auto piece = [&](int g, hipStream_t s, auto direct) -> hipError_t {
         return use_graph ? hipGraphLaunch(c->graph_exec[g], s) : direct();
     };
-    hipError_t e = piece(wse_ctx::G_FILL, c->rs, [&] { return launch_round_fill(c->arena, c->d_rd.p, groups, c->rs); });
+    const WorkEntry* work = m.work->p;
+    hipError_t e = piece(wse_ctx::G_FILL, c->rs, [&] { return launch_round_fill(m.arena, m.rd, groups, c->rs); });
     if (e == hipSuccess) e = hipEventRecord(c->fork, c->rs);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->rs2, c->fork, 0);
     if (e == hipSuccess) e = hipEventRecord(c->dl_t0, c->rs2);
     if (e == hipSuccess && (use_graph || counts[LIST_EVAL_DL]))
         e = piece(wse_ctx::G_DL, c->rs2, [&] {
-            return launch_eval(c->d_work.p, c->d_rd.p, LIST_EVAL_DL, t, c->lds_slots, groups, c->rs2);
+            return launch_eval(work, m.rd, LIST_EVAL_DL, t, c->lds_slots, groups, c->rs2);
         });
     if (e == hipSuccess) e = hipEventRecord(c->dl_t1, c->rs2);
     if (e == hipSuccess) e = hipEventRecord(c->join, c->rs2);
@@ -864,7 +944,7 @@ static hipError_t launch_round(wse_ctx* c, DevTables t, int64_t groups, bool use
         e = piece(wse_ctx::G_GEN, c->rs, [&] {
             hipError_t r = hipSuccess;
             for (int w = LIST_EVAL_A; w <= LIST_EVAL_B && r == hipSuccess; w++)
-                if (counts[w]) r = launch_eval(c->d_work.p, c->d_rd.p, w, t, c->lds_slots, groups, c->rs);
+                if (counts[w]) r = launch_eval(work, m.rd, w, t, c->lds_slots, groups, c->rs);
             return r;
         });
     if (e == hipSuccess) e = hipStreamWaitEvent(c->rs, c->join, 0);
@@ -910,8 +990,8 @@ static wse_status ensure_round_graphs(wse_ctx* c, int64_t groups)
 // Evaluation and counting launches of one round; all tables of the round
 // live in the arena at once.  Batched rounds replay the captured graphs;
 // plain rounds launch the same kernels one by one.
-static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hipStream_t st, bool use_graph,
-                            float* eval_ms, float* count_ms)
+static wse_status run_round(wse_ctx* c, RoundMem m, const std::vector<RoundItem>& round, hipStream_t st,
+                            bool use_graph, float* eval_ms, float* count_ms)
 {
     std::vector<WorkEntry> all;
     int64_t items[N_LISTS] = {0, 0, 0, 0}, used = 0;
@@ -931,7 +1011,7 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
             WorkEntry e;
             e.cfg = r.job->d_cfgs.p + r.id;
             e.ctr = r.job->d_ctr.p + r.id;
-            e.tables = c->arena + base;
+            e.tables = m.arena + base;
             e.what = what;
             e.pad = 0;
             e.n_units = units;
@@ -946,13 +1026,15 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
         // sector table, so it runs in the launch after the wave pass
         const bool lattice_bitmap = g.kind == 0 && (g.dense & 2) != 0;
         // row ranges: lattice bitmap passes whose element fits a sector
-        const bool rows = c->row_ranges && lattice_bitmap && g.uniform_elem > 0 &&
-                          g.uniform_elem <= c->hws[g.hw_id].sector_bytes;
+        const bool rows = c->row_ranges && lattice_bitmap && g.row_ok;
         const int64_t row_len = std::max<int64_t>(1, g.T[0]);
         int64_t per_rows = std::max<int64_t>(1, c->target_evals / (row_len * std::max(1, g.E)));
         per_rows = (per_rows + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
         add(LIST_EVAL_A, PASS_B, spb, per);
-        if (rows) add(LIST_EVAL_DL, PASS_WR, g.w_rows, per_rows);
+        if (rows) {
+            add(LIST_EVAL_DL, PASS_WR, g.w_rows, per_rows);
+            c->last_row_units += g.w_rows + (g.smin >= 0 ? g.l_rows : 0);
+        }
         else add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_W, g.w_units, per);
         // the warp-level store counts of the wave evaluate store instructions only
         const int n_st = std::max(1, g.E - g.n_ld);
@@ -974,24 +1056,30 @@ static wse_status run_round(wse_ctx* c, const std::vector<RoundItem>& round, hip
         all.insert(all.end(), lists[w].begin(), lists[w].end());
     }
     c->last_table_bytes += used;
-    HIP_TRY(c->d_work.reserve(std::max<size_t>(all.size(), 1)));
-    HIP_TRY(c->d_rd.reserve(1));
+    HIP_TRY(m.work->reserve(std::max<size_t>(all.size(), 1)));
+    if (!m.rd) {
+        HIP_TRY(c->d_rd.reserve(1));
+        m.rd = c->d_rd.p;
+    }
     const int64_t groups = (int64_t)c->n_cu * c->groups_per_cu;
+    // the captured graphs name the context's arena, work list and descriptor
+    if (use_graph && (m.arena != c->arena || m.work != &c->d_work || m.expansions))
+        return fail(WSE_EINVAL, "graph rounds run in the context's own memory only");
     if (use_graph) WSE_TRY(ensure_round_graphs(c, groups));
     // the round runs on the round stream after everything queued on st
     c->round_events.used = 0;
     hipEvent_t dep = c->round_events.mark(st);
     HIP_TRY(hipStreamWaitEvent(c->rs, dep, 0));
     if (!all.empty())
-        HIP_TRY(hipMemcpyAsync(c->d_work.p, all.data(), all.size() * sizeof(WorkEntry), hipMemcpyHostToDevice, c->rs));
-    HIP_TRY(hipMemcpyAsync(c->d_rd.p, &rd, sizeof(rd), hipMemcpyHostToDevice, c->rs));
+        HIP_TRY(hipMemcpyAsync(m.work->p, all.data(), all.size() * sizeof(WorkEntry), hipMemcpyHostToDevice, c->rs));
+    HIP_TRY(hipMemcpyAsync(m.rd, &rd, sizeof(rd), hipMemcpyHostToDevice, c->rs));
     hipEvent_t e0 = c->round_events.mark(c->rs);
-    HIP_TRY(launch_round(c, dev_tables(c, nullptr, 0), groups, use_graph, counts));
+    HIP_TRY(launch_round(c, m, dev_tables(c, nullptr, 0, m.expansions), groups, use_graph, counts));
     hipEvent_t e1 = c->round_events.mark(c->rs);
     if (use_graph) {
         HIP_TRY(hipGraphLaunch(c->graph_exec[wse_ctx::G_COUNT], c->rs));
     } else if (counts[LIST_COUNT]) {
-        HIP_TRY(launch_count(c->d_work.p, c->d_rd.p, groups, c->rs));
+        HIP_TRY(launch_count(m.work->p, m.rd, groups, c->rs));
     }
     hipEvent_t e2 = c->round_events.mark(c->rs);
     // the host reuses the work list, the round descriptor and the arena next round
@@ -1024,6 +1112,51 @@ extern "C" wse_status wse_space_size(wse_ctx* c, const wse_space* s, int64_t* n)
     return WSE_OK;
 }
 
+// One request through its arena rounds: decode, rounds in `m`, model and
+// ranks, then the statistics the wse_last_* calls report.  Caller holds c->mu.
+static wse_status estimate_job(wse_ctx* c, Job& j, const RoundMem& m, bool batched, bool use_graph,
+                               hipStream_t st)
+{
+    c->last_table_bytes = c->last_launches = c->last_rounds = 0;
+    c->last_dl_ms = 0;
+    c->last_dl_launches = 0;
+    c->last_row_units = 0;
+    c->events.used = 0;
+    hipEvent_t t0 = c->events.mark(st);
+    WSE_TRY(job_prepare(c, j, st, m.arena_bytes));
+    hipEvent_t t1 = c->events.mark(st);
+    float eval_ms = 0.f, count_ms = 0.f;
+    std::vector<Job*> jobs{&j};
+    std::vector<RoundItem> round;
+    size_t limit = batched ? SIZE_MAX : 1;
+    while (j.next < j.runnable.size()) {
+        form_round(c, m, jobs, round, limit);
+        WSE_TRY(run_round(c, m, round, st, use_graph, &eval_ms, &count_ms));
+    }
+    hipEvent_t t2 = c->events.mark(st);
+    WSE_TRY(job_finish(c, j, st));
+    hipEvent_t t3 = c->events.mark(st);
+    HIP_TRY(hipStreamSynchronize(st));
+    c->timings[0] = elapsed(t0, t1);
+    c->timings[1] = eval_ms;
+    c->timings[2] = count_ms;
+    c->timings[3] = elapsed(t2, t3);
+    c->timings[4] = c->last_dl_ms;
+    c->last_total = j.total;
+    c->last_ctr.resize(j.total);
+    c->last_E.resize(j.total);
+    c->last_dense = 0;
+    c->last_dl.resize(j.total);
+    for (int64_t i = 0; i < j.total; i++) {
+        const Cfg& g = j.cfgs[i];
+        c->last_E[i] = g.status == 0 ? g.E : 0;
+        c->last_dense += g.status == 0 && g.dense != 0;
+        c->last_dl[i] = g.status == 0 && g.kind == 0 && (g.dense & 2) != 0;
+    }
+    HIP_TRY(hipMemcpy(c->last_ctr.data(), j.d_ctr.p, j.total * sizeof(Counters), hipMemcpyDeviceToHost));
+    return WSE_OK;
+}
+
 extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t n_spaces, wse_result* out,
                                    int32_t* rank_out, int64_t out_capacity, int32_t mode, void* stream)
 {
@@ -1031,7 +1164,6 @@ extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t 
     if (mode != WSE_PLAIN && mode != WSE_BATCHED) return fail(WSE_EINVAL, "unknown mode");
     std::lock_guard<std::mutex> lk(c->mu);
     HIP_TRY(hipSetDevice(c->device));
-    hipStream_t st = (hipStream_t)stream;
     Job j;
     WSE_TRY(job_init(c, j, spaces, n_spaces));
     if (j.total > out_capacity) return fail(WSE_EINVAL, "out_capacity is smaller than the number of configurations");
@@ -1039,56 +1171,8 @@ extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t 
     if (j.total == 0) return WSE_OK;
     j.out = out;
     j.rank_out = rank_out;
-    c->last_table_bytes = c->last_launches = c->last_rounds = 0;
-    c->last_dl_ms = 0;
-    c->last_dl_launches = 0;
-    c->events.used = 0;
-    hipEvent_t t0 = c->events.mark(st);
-    wse_status s = job_prepare(c, j, st);
-    if (s != WSE_OK) {
-        j.release();
-        return s;
-    }
-    hipEvent_t t1 = c->events.mark(st);
-    float eval_ms = 0.f, count_ms = 0.f;
-    std::vector<Job*> jobs{&j};
-    std::vector<RoundItem> round;
-    size_t limit = mode == WSE_BATCHED ? SIZE_MAX : 1;
-    while (j.next < j.runnable.size()) {
-        form_round(c, jobs, round, limit);
-        s = run_round(c, round, st, mode == WSE_BATCHED, &eval_ms, &count_ms);
-        if (s != WSE_OK) {
-            j.release();
-            return s;
-        }
-    }
-    hipEvent_t t2 = c->events.mark(st);
-    s = job_finish(c, j, st);
-    hipEvent_t t3 = c->events.mark(st);
-    if (s == WSE_OK) {
-        hipError_t e = hipStreamSynchronize(st);
-        if (e != hipSuccess) s = fail(WSE_EDEVICE, hipGetErrorString(e));
-    }
-    if (s == WSE_OK) {
-        c->timings[0] = elapsed(t0, t1);
-        c->timings[1] = eval_ms;
-        c->timings[2] = count_ms;
-        c->timings[3] = elapsed(t2, t3);
-        c->timings[4] = c->last_dl_ms;
-        c->last_total = j.total;
-        c->last_ctr.resize(j.total);
-        c->last_E.resize(j.total);
-        c->last_dense = 0;
-        c->last_dl.resize(j.total);
-        for (int64_t i = 0; i < j.total; i++) {
-            const Cfg& g = j.cfgs[i];
-            c->last_E[i] = g.status == 0 ? g.E : 0;
-            c->last_dense += g.status == 0 && g.dense != 0;
-            c->last_dl[i] = g.status == 0 && g.kind == 0 && (g.dense & 2) != 0;
-        }
-        hipError_t e = hipMemcpy(c->last_ctr.data(), j.d_ctr.p, j.total * sizeof(Counters), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) s = fail(WSE_EDEVICE, hipGetErrorString(e));
-    }
+    wse_status s = estimate_job(c, j, ctx_round_mem(c), mode == WSE_BATCHED, mode == WSE_BATCHED,
+                                (hipStream_t)stream);
     j.release();
     return s;
 }
@@ -1104,9 +1188,9 @@ extern "C" wse_status wse_last_stats(wse_ctx* c, int64_t* stats, int32_t n)
     for (int64_t i = 0; i < c->last_total; i++)
         if (c->last_dl[i])
             dl_evals += (int64_t)(c->last_ctr[i].lanes_W + c->last_ctr[i].lanes_L) * c->last_E[i];
-    int64_t v[8] = {evals, c->last_table_bytes, c->last_launches, c->last_rounds, c->last_total, c->last_dense,
-                    dl_evals, c->last_dl_launches};
-    for (int i = 0; i < n && i < 8; i++) stats[i] = v[i];
+    int64_t v[9] = {evals, c->last_table_bytes, c->last_launches, c->last_rounds, c->last_total, c->last_dense,
+                    dl_evals, c->last_dl_launches, c->last_row_units};
+    for (int i = 0; i < n && i < 9; i++) stats[i] = v[i];
     return WSE_OK;
 }
 
@@ -1218,14 +1302,15 @@ static wse_status timed_run(wse_ctx* c, const std::vector<wse_space>& spaces, hi
     HIP_TRY(out.reserve(std::max<int64_t>(j.total, 1)));
     j.out = (wse_result*)out.p;
     j.rank_out = nullptr;
-    wse_status s = job_prepare(c, j, st);
+    const RoundMem m = ctx_round_mem(c);
+    wse_status s = job_prepare(c, j, st, m.arena_bytes);
     float ev = 0.f, cn = 0.f;
     std::vector<Job*> jobs{&j};
     std::vector<RoundItem> round;
     auto t0 = std::chrono::steady_clock::now();
     while (s == WSE_OK && j.next < j.runnable.size()) {
-        form_round(c, jobs, round, SIZE_MAX);
-        s = run_round(c, round, st, true, &ev, &cn);
+        form_round(c, m, jobs, round, SIZE_MAX);
+        s = run_round(c, m, round, st, true, &ev, &cn);
     }
     if (s == WSE_OK) s = job_finish(c, j, st);
     auto t1 = std::chrono::steady_clock::now();
@@ -1326,8 +1411,9 @@ static void server_loop(wse_server* S)
         std::vector<std::shared_ptr<Job>> finished;
         {
             std::lock_guard<std::mutex> dk(c->mu);
+            const RoundMem m = ctx_round_mem(c);
             for (auto& j : admitted) {
-                wse_status s = job_prepare(c, *j, S->stream);
+                wse_status s = job_prepare(c, *j, S->stream, m.arena_bytes);
                 if (s != WSE_OK) {
                     j->status = s;
                     j->error = g_err;
@@ -1337,9 +1423,9 @@ static void server_loop(wse_server* S)
             for (auto& j : active)
                 if (j->status == WSE_OK && j->prepared && j->next < j->runnable.size()) runnable.push_back(j.get());
             if (!runnable.empty()) {
-                form_round(c, runnable, round, SIZE_MAX);
+                form_round(c, m, runnable, round, SIZE_MAX, S->opts.round_evals);
                 float ev = 0.f, cn = 0.f;
-                wse_status s = run_round(c, round, S->stream, true, &ev, &cn);
+                wse_status s = run_round(c, m, round, S->stream, true, &ev, &cn);
                 if (s != WSE_OK) {
                     for (const RoundItem& r : round) {
                         r.job->status = s;
@@ -1384,6 +1470,7 @@ extern "C" wse_status wse_server_start(wse_ctx* c, const wse_server_opts* opts, 
     S->opts.memory_budget_bytes = opts && opts->memory_budget_bytes ? opts->memory_budget_bytes : ((size_t)8 << 30);
     S->opts.max_inflight = opts && opts->max_inflight > 0 ? opts->max_inflight : 64;
     S->opts.max_queue = opts && opts->max_queue > 0 ? opts->max_queue : 1000000;
+    S->opts.round_evals = opts && opts->round_evals > 0 ? opts->round_evals : ((int64_t)1 << 37);
     hipError_t e = hipSetDevice(c->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {

@@ -57,7 +57,7 @@ struct KernelDev {
     const void* items;     // lattice: AccessL[n_items]; affine: ExprA[n_items]
     double flops_per_lup;
     int32_t uniform_elem;  // all fields share one element size (0 if not)
-    int32_t pad;
+    int32_t multidim;      // lattice kernel counted in the multi-dimensional address space
 };
 
 struct AccessL {
@@ -116,8 +116,15 @@ struct Cfg {
     int32_t dense;              // bitmaps instead of hash tables: bit 0 the block pass's
                                 // tables, bit 1 the wave and layer passes'; bit 2: the wave's
                                 // lines are counted from its sector bitmaps (no line table)
-    int32_t pad2;
+    int32_t row_ok;             // lattice kernel of one element size no larger than a sector:
+                                // its wave and layer sets can be filled by row ranges
     int64_t sy, sz, g;
+    // address layout of the wave and layer passes (the block pass uses sy, sz
+    // and the fields' alignments): the same as the block pass's, or, in the
+    // multi-dimensional address space, every array row on a line boundary of
+    // its own, rows wsy elements apart, planes wsz, all fields based at wabase
+    int64_t wsy, wsz, wabase;
+    int32_t multidim, pad3;
     int64_t evals[3];           // thread x instruction evaluations per pass (upper bound)
     int64_t l_units;            // layer pass: segments of its blocks' threads in row order
     int64_t w_units;            // wave pass: segments of its blocks' threads in row order

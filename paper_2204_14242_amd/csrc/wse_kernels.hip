@@ -28,17 +28,6 @@ namespace wse {
 
 // ------------------------------------------------------------------ helpers
 
-// 64-bit mixing function (MurmurHash3 finaliser)
-__device__ __forceinline__ uint64_t mix64(uint64_t k)
-{
-    k ^= k >> 33;
-    k *= 0xff51afd7ed558ccdULL;
-    k ^= k >> 33;
-    k *= 0xc4ceb9fe1a85ec53ULL;
-    k ^= k >> 33;
-    return k;
-}
-
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kLanes - 1)); }
 
 __device__ __forceinline__ int64_t readlane64(int64_t v, int l)
@@ -95,6 +84,7 @@ __device__ __forceinline__ uint32_t slot_of(uint64_t key1, int log2cap)
 __device__ __forceinline__ int set_insert(unsigned long long* slots, int log2cap, uint64_t entry, int pb,
                                           int mode)
 {
+    if (log2cap <= 0) return -1;  // a table with no slots (a layout error): reported as overflow
     const uint64_t key1 = entry >> pb;
     const uint32_t mask = (uint32_t)(((uint64_t)1 << log2cap) - 1);
     uint32_t pos = slot_of(key1, log2cap);
@@ -122,6 +112,7 @@ __device__ __forceinline__ int set_insert(unsigned long long* slots, int log2cap
 __device__ __forceinline__ int table_insert(unsigned long long* slots, int log2cap, uint64_t entry, int pb,
                                             int mode)
 {
+    if (log2cap <= 0) return -1;  // a table with no slots (a layout error): reported as overflow
     const uint64_t key1 = entry >> pb;
     const uint32_t mask = (uint32_t)(((uint64_t)1 << log2cap) - 1);
     uint32_t pos = slot_of(key1, log2cap);
@@ -148,6 +139,7 @@ __device__ __forceinline__ int table_insert(unsigned long long* slots, int log2c
 __device__ __forceinline__ int64_t set_find(const unsigned long long* slots, int log2cap, uint64_t key1,
                                             int pb)
 {
+    if (log2cap <= 0) return -1;
     const uint32_t mask = (uint32_t)(((uint64_t)1 << log2cap) - 1);
     uint32_t pos = slot_of(key1, log2cap);
     for (uint64_t probe = 0; probe <= mask; probe++) {
@@ -332,7 +324,7 @@ struct Range {
 // smallest and largest unit (address >> log2u) any valid thread of the
 // blocks [klo, khi) reaches with any instruction
 __device__ void unit_range(const Cfg& c, const KernelDev& K, const Expansion* X, int64_t klo,
-                           int64_t khi, int log2u, int64_t* umin, int64_t* umax, int* bad)
+                           int64_t khi, int log2u, bool wave, int64_t* umin, int64_t* umax, int* bad)
 {
     int64_t nxy = c.nb[0] * c.nb[1];
     int64_t blo[3], bhi[3];
@@ -366,17 +358,20 @@ __device__ void unit_range(const Cfg& c, const KernelDev& K, const Expansion* X,
             int64_t h = (bhi[d] + 1) * c.b[d];
             ghi[d] = (h < c.T[d] ? h : c.T[d]) - 1;
         }
-        __int128 blo_ = (__int128)(glo[0] + c.g) + (__int128)c.sy * (c.fold[1] * glo[1] + c.g) +
-                        (__int128)c.sz * (c.fold[2] * glo[2] + c.g);
-        __int128 bhi_ = (__int128)(ghi[0] + c.g) + (__int128)c.sy * (c.fold[1] * ghi[1] + c.g) +
-                        (__int128)c.sz * (c.fold[2] * ghi[2] + c.g);
+        const int64_t sy = wave ? c.wsy : c.sy, sz = wave ? c.wsz : c.sz;
+        const bool md = wave && c.multidim;
+        __int128 blo_ = (__int128)(glo[0] + c.g) + (__int128)sy * (c.fold[1] * glo[1] + c.g) +
+                        (__int128)sz * (c.fold[2] * glo[2] + c.g);
+        __int128 bhi_ = (__int128)(ghi[0] + c.g) + (__int128)sy * (c.fold[1] * ghi[1] + c.g) +
+                        (__int128)sz * (c.fold[2] * ghi[2] + c.g);
         const ExprL* ex = X->ex;
         for (int e = 0; e < c.E; e++) {
             int f = ex[e].f;
             int64_t elem = c.elem ? c.elem : K.elem[f];
-            __int128 c0 = (__int128)ex[e].v[0] + (__int128)c.sy * ex[e].v[1] + (__int128)c.sz * ex[e].v[2];
-            __int128 a0 = (__int128)K.align[f] + (__int128)elem * (blo_ + c0);
-            __int128 a1 = (__int128)K.align[f] + (__int128)elem * (bhi_ + c0);
+            __int128 c0 = (__int128)ex[e].v[0] + (__int128)sy * ex[e].v[1] + (__int128)sz * ex[e].v[2];
+            const __int128 base = md ? (__int128)c.wabase : (__int128)K.align[f];
+            __int128 a0 = base + (__int128)elem * (blo_ + c0);
+            __int128 a1 = base + (__int128)elem * (bhi_ + c0);
             if (a0 < -LIM || a1 >= LIM) {
                 *bad = 1;
                 return;
@@ -486,17 +481,67 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         c.E = X.E;
         c.n_ld = X.n_ld;
         c.uniform_elem = c.elem ? c.elem : K.uniform_elem;
-        // offsets of the expanded instructions, for the evaluation's
-        // per-segment range proofs
+        c.row_ok = c.uniform_elem > 0 && c.uniform_elem <= H.sector_bytes;
+        c.wsy = c.sy;
+        c.wsz = c.sz;
+        c.wabase = 0;
+        c.multidim = 0;
+        if (K.multidim) {
+            // Multi-dimensional address space (Sec. 4.4.1) for the wave and
+            // layer sets: a point names (field, z, y, x) instead of a linear
+            // address.  Laid out so that every array row the configuration
+            // reaches starts on a line boundary of its own and holds all of
+            // its x, two points share a sector or line exactly when their
+            // tuples do: rows wsy elements apart (a multiple of the line size
+            // and of the element), x shifted by a line multiple so that the
+            // smallest x reached sits at or after the row start.
+            const int64_t E1 = c.uniform_elem;
+            if (E1 <= 0) {
+                c.status = -1;  // needs one element size
+                cfgs[i] = c;
+                return;
+            }
+            int64_t vmin[3] = {0, 0, 0}, vmax[3] = {0, 0, 0};
+            for (int e = 0; e < c.E; e++)
+                for (int d = 0; d < 3; d++) {
+                    const int64_t v = X.ex[e].v[d];
+                    if (e == 0 || v < vmin[d]) vmin[d] = v;
+                    if (e == 0 || v > vmax[d]) vmax[d] = v;
+                }
+            const int64_t xlo = c.g + vmin[0], xhi = c.g + c.T[0] - 1 + vmax[0];
+            const int64_t ylo = c.g + vmin[1], yhi = c.g + c.fold[1] * (c.T[1] - 1) + vmax[1];
+            const int64_t zlo = c.g + vmin[2];
+            int64_t a = H.line_bytes, b = E1;   // q = lcm(line, elem) / elem elements
+            while (b) {
+                const int64_t t = a % b;
+                a = b;
+                b = t;
+            }
+            const int64_t q = H.line_bytes / a;
+            const int64_t sx = xlo < 0 ? (-xlo + q - 1) / q * q : 0;
+            c.wsy = (xhi + sx + 1 + q - 1) / q * q;
+            c.wsz = c.wsy * (yhi - ylo + 1);
+            const __int128 wb = (__int128)E1 * ((__int128)sx - (__int128)c.wsy * ylo - (__int128)c.wsz * zlo);
+            const __int128 LIM = (__int128)1 << 62;
+            if (wb <= -LIM || wb >= LIM) {
+                c.status = -3;
+                cfgs[i] = c;
+                return;
+            }
+            c.wabase = (int64_t)wb;
+            c.multidim = 1;
+        }
+        // offsets of the expanded instructions (wave and layer layout), for
+        // the evaluation's per-segment range proofs
         c.s_lo = 1;
         c.s_hi = 0;
         if (c.uniform_elem > 0) {
             __int128 lo = 0, hi = 0;
             for (int e = 0; e < c.E; e++) {
                 const ExprL& x = X.ex[e];
-                const __int128 S = (__int128)K.align[x.f] +
-                                   (__int128)c.uniform_elem * ((__int128)x.v[0] + (__int128)c.sy * x.v[1] +
-                                                               (__int128)c.sz * x.v[2]);
+                const __int128 S = (c.multidim ? (__int128)c.wabase : (__int128)K.align[x.f]) +
+                                   (__int128)c.uniform_elem * ((__int128)x.v[0] + (__int128)c.wsy * x.v[1] +
+                                                               (__int128)c.wsz * x.v[2]);
                 if (e == 0 || S < lo) lo = S;
                 if (e == 0 || S > hi) hi = S;
             }
@@ -602,7 +647,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         T.pb = pbs[q];
         if (khi[q] <= klo[q] || klo[q] < 0 || ev[q] == 0) continue;
         int64_t umin = 0, umax = 0;
-        unit_range(c, K, X, klo[q], khi[q], gran[q], &umin, &umax, &bad);
+        unit_range(c, K, X, klo[q], khi[q], gran[q], q >= T_WSEC, &umin, &umax, &bad);
         if (bad) break;
         T.umin = umin;
         T.span = umax - umin + 1;
@@ -630,6 +675,8 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
     // sectors outside the wave's exact sector range count for no shell, which
     // intersects them with the wave's load sectors.)
     bool w_lines_derived = false;
+    const int64_t wsec_umin = c.tab[T_WSEC].umin, wsec_span = c.tab[T_WSEC].span;
+    const uint64_t wsec_keys = keys_of[T_WSEC], wline_keys = keys_of[T_WLINE];
     {
         const int lr = H.log2_line - H.log2_sector;
         const TableDesc& L = c.tab[T_WLINE];
@@ -667,7 +714,17 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
                 int64_t n_bm = r == T_WSEC ? 2 + (c.smin >= 0 ? c.n_order : 0) : (r == T_LLINE ? c.n_order : 1);
                 need += dense_g[r >= T_WSEC] ? n_bm * w * 4 + 512 : ((int64_t)12 << l2_of[r]) + 512;
             }
-            if (need >= ((int64_t)1 << 33)) dense_g[0] = dense_g[1] = false;
+            if (need >= ((int64_t)1 << 33)) {
+                dense_g[0] = dense_g[1] = false;
+                // hash tables keep the wave's lines in a table of their own
+                if (w_lines_derived) {
+                    c.tab[T_WSEC].umin = wsec_umin;
+                    c.tab[T_WSEC].span = wsec_span;
+                    keys_of[T_WSEC] = wsec_keys;
+                    keys_of[T_WLINE] = wline_keys;
+                    w_lines_derived = false;
+                }
+            }
         }
         if (keys_of[q] == 0) continue;
         T.off = bytes;
@@ -797,12 +854,105 @@ __device__ __forceinline__ int64_t warp_distinct(bool valid, int64_t v, int log2
     return cnt;
 }
 
+// Reductions over aligned groups of 2^log2g <= 16 lanes inside the DPP rows
+// of 16 lanes: partners at lane ^ 1 and lane ^ 2 (quad permutations), then
+// the mirrored lane of the half row and of the row, so that after log2g
+// steps every lane of a group holds the group's result.
+template <int STEP>
+__device__ __forceinline__ uint32_t row_partner(uint32_t v)
+{
+    constexpr int ctrl = STEP == 0 ? 0xb1 : (STEP == 1 ? 0x4e : (STEP == 2 ? 0x141 : 0x140));
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, ctrl, 0xf, 0xf, false);
+}
+
+template <int STEP>
+__device__ __forceinline__ void row_min64_step(int64_t& v, int log2g)
+{
+    if (STEP >= log2g) return;
+    const uint32_t lo = row_partner<STEP>((uint32_t)(uint64_t)v);
+    const uint32_t hi = row_partner<STEP>((uint32_t)((uint64_t)v >> 32));
+    const int64_t o = (int64_t)(((uint64_t)hi << 32) | lo);
+    v = o < v ? o : v;
+}
+
+template <int STEP>
+__device__ __forceinline__ void row_or_step(uint32_t& v, int log2g)
+{
+    if (STEP < log2g) v |= row_partner<STEP>(v);
+}
+
+template <int STEP>
+__device__ __forceinline__ void row_max_step(uint32_t& v, int log2g)
+{
+    if (STEP >= log2g) return;
+    const uint32_t o = row_partner<STEP>(v);
+    v = o > v ? o : v;
+}
+
+// group_cycles for groups of at most 16 lanes, at most 32 banks and pairing
+// spans of at most 128 words, with DPP row operations only.  For each
+// cluster: the group's smallest remaining word m (a row reduction), the
+// cluster's words as bits d = w - m of a 128-bit mask (an OR reduction: a word
+// named by several lanes is one bit), and the count of bank b as the bits of
+// the mask whose word falls in bank b: every bank size divides 32, so bank b
+// holds positions d = (b - m) mod n_banks + k * n_banks of every 32-bit mask word.
+__device__ __forceinline__ int64_t group_cycles_rows(bool valid, int64_t w, int log2g, int nbanks,
+                                                     int pair_words)
+{
+    const int lane = lane_id();
+    const int gl = 1 << log2g;
+    const int glane = lane & (gl - 1);
+    const int nw = (pair_words + 31) >> 5;
+    uint32_t pat = 0;
+    for (int k = 0; k < 32; k += nbanks) pat |= 1u << k;
+    bool remn = valid;
+    int64_t cyc = 0;
+    while (__ballot(remn)) {
+        int64_t m = remn ? w : INT64_MAX;
+        row_min64_step<0>(m, log2g);
+        row_min64_step<1>(m, log2g);
+        row_min64_step<2>(m, log2g);
+        row_min64_step<3>(m, log2g);
+        const int64_t d = w - m;
+        const bool mem = remn && d < (int64_t)pair_words;
+        uint32_t M[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            M[q] = (mem && (d >> 5) == q) ? 1u << (d & 31) : 0u;
+            if (q < nw) {
+                row_or_step<0>(M[q], log2g);
+                row_or_step<1>(M[q], log2g);
+                row_or_step<2>(M[q], log2g);
+                row_or_step<3>(M[q], log2g);
+            }
+        }
+        uint32_t cnt = 0;
+        for (int b = glane; b < nbanks; b += gl) {
+            const uint32_t pr = pat << ((uint32_t)(b - (int)(m & (int64_t)(nbanks - 1))) & (uint32_t)(nbanks - 1));
+            uint32_t c = 0;
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (q < nw) c += (uint32_t)__popc(M[q] & pr);
+            cnt = c > cnt ? c : cnt;
+        }
+        row_max_step<0>(cnt, log2g);
+        row_max_step<1>(cnt, log2g);
+        row_max_step<2>(cnt, log2g);
+        row_max_step<3>(cnt, log2g);
+        if (glane == 0) cyc += cnt;
+        remn = remn && !mem;
+    }
+    return wave_sum64(cyc);
+}
+
 // L1 cycles of every group of 2^log2g lanes for one instruction (Sec. 4.2):
 // distinct bank words, greedy clusters of span < pair_words, each costing
 // its largest per-bank word count.  Returns the wave's total.
 __device__ __forceinline__ int64_t group_cycles(bool valid, int64_t w, int log2g, int nbanks,
                                                 int64_t pair_words)
 {
+    if (log2g <= 4 && nbanks <= 32 && pair_words <= 128)
+        return group_cycles_rows(valid, w, log2g, nbanks, (int)pair_words);
     const int lane = lane_id();
     const int gl = 1 << log2g;
     const int glane = lane & (gl - 1);
@@ -972,7 +1122,8 @@ struct IConst {
     uint64_t SL;
 };
 
-template <int KIND>
+// WAVE: the wave and layer passes' address layout (Cfg::wsy, wsz, wabase)
+template <int KIND, bool WAVE>
 __device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, TableR& TS, TableR& TL)
 {
     CfgR& c = *P.c;
@@ -983,8 +1134,9 @@ __device__ __forceinline__ IConst load_iconst(const PassCtx& P, int e, TableR& T
         f = x.f;
         r.st = x.st;
         r.elem = c.elem ? c.elem : P.K->elem[f];
-        int64_t c0 = (int64_t)x.v[0] + c.sy * x.v[1] + c.sz * x.v[2];
-        r.S = P.K->align[f] + (int64_t)r.elem * c0;
+        const int64_t sy = WAVE ? c.wsy : c.sy, sz = WAVE ? c.wsz : c.sz;
+        int64_t c0 = (int64_t)x.v[0] + sy * x.v[1] + sz * x.v[2];
+        r.S = (WAVE && c.multidim ? c.wabase : P.K->align[f]) + (int64_t)r.elem * c0;
         for (int d = 0; d < 3; d++) {
             r.kt[d] = 0;
             r.kb[d] = 0;
@@ -1197,7 +1349,7 @@ __device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, 
     const int64_t b0 = c.b[0], b1 = c.b[1], b2 = c.b[2];
     const int lb1 = c.lb[1];
     const int64_t T0 = c.T[0], T1 = c.T[1], T2 = c.T[2];
-    const int64_t sy = c.sy, sz = c.sz, g = c.g, f1 = c.fold[1], f2 = c.fold[2];
+    const int64_t sy = c.wsy, sz = c.wsz, g = c.g, f1 = c.fold[1], f2 = c.fold[2];
     const int64_t uelem = c.uniform_elem;
     TableR& TS = c.tab[T_WSEC];
     TableR& TL = c.tab[PASS == PASS_L ? T_LLINE : T_WLINE];
@@ -1215,7 +1367,7 @@ __device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, 
     for (int e0 = 0; e0 < E; e0 += kLanes) {
         const bool mine = e0 + lane < E;
         IConst ic;
-        if (mine) ic = load_iconst<0>(P, e0 + lane, TS, TL);
+        if (mine) ic = load_iconst<0, true>(P, e0 + lane, TS, TL);
         else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}, 0};
         for (int64_t u = j0 + P.wave; u < j1; u += kWavesPerGroup) {
             const int64_t r = ro.r0 + u / rows_per;
@@ -1303,7 +1455,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     const int lb0 = c.lb[0], lb1 = c.lb[1];
     const int64_t T0 = c.T[0], T1 = c.T[1], T2 = c.T[2];
     const int64_t Pthr = c.P;
-    const int64_t sy = c.sy, sz = c.sz, g = c.g;
+    // the block pass reads the fields' own layout, the others the wave layout
+    const int64_t sy = PASS == PASS_B ? c.sy : c.wsy, sz = PASS == PASS_B ? c.sz : c.wsz, g = c.g;
     const int64_t f1 = c.fold[1], f2 = c.fold[2];
     const int64_t smin = c.smin;
     const int tag_bits = c.tag_bits;
@@ -1337,7 +1490,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     for (int e0 = 0; e0 < E; e0 += kLanes) {
         const int n_in = E - e0 < kLanes ? E - e0 : kLanes;
         IConst ic;
-        if (e0 + lane < E) ic = load_iconst<KIND>(P, e0 + lane, TS, TL);
+        if (e0 + lane < E) ic = load_iconst<KIND, PASS != PASS_B>(P, e0 + lane, TS, TL);
         else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}, 0};
         const int32_t meta = ic.st | (ic.elem << 1);
 

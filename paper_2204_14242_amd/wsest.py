@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libwsest.so")
 
 WSE_OK, WSE_EINVAL, WSE_ENOMEM, WSE_ERANGE, WSE_EDEVICE, WSE_EBUSY, WSE_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
 PLAIN, BATCHED = 0, 1
+ADDR_LINEAR, ADDR_MULTIDIM = 0, 1
 KERNEL_LATTICE, KERNEL_AFFINE = 0, 1
 
 RESULT_DTYPE = np.dtype([
@@ -51,7 +52,7 @@ class wse_access(C.Structure):
 class wse_kernel_desc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_fields", C.c_int32), ("n_items", C.c_int32),
                 ("ghost", C.c_int32), ("fields", C.POINTER(wse_field)), ("items", C.c_void_p),
-                ("flops_per_lup", C.c_double)]
+                ("flops_per_lup", C.c_double), ("address_space", C.c_int32), ("pad", C.c_int32)]
 
 
 class wse_fit(C.Structure):
@@ -84,7 +85,7 @@ class wse_tuning(C.Structure):
 
 class wse_server_opts(C.Structure):
     _fields_ = [("memory_budget_bytes", C.c_size_t), ("max_inflight", C.c_int32),
-                ("max_queue", C.c_int32)]
+                ("max_queue", C.c_int32), ("round_evals", C.c_int64)]
 
 
 _lib = None
@@ -213,6 +214,7 @@ class Context:
         d.n_fields = len(kernel["fields"])
         d.fields = fields
         d.flops_per_lup = float(kernel.get("flops_per_lup", 0.0))
+        d.address_space = ADDR_MULTIDIM if kernel.get("address_space") == "multidim" else ADDR_LINEAR
         if kernel["kind"] == "lattice":
             acc = kernel["accesses"]
             items = (wse_access * len(acc))()
@@ -294,6 +296,9 @@ class Context:
         the results come back as host numpy arrays; torch CUDA tensors (uint8
         of n*400 bytes, int32 of n) may be passed to keep results on the
         device.  Returns (results, ranks)."""
+        return self._estimate(specs, mode, out, rank, stream)
+
+    def _estimate(self, specs, mode, out, rank, stream):
         keep = []
         arr = self.spaces_array(specs, keep)
         n = sum(self.space_size(k, h, sp) for (k, h, sp) in specs)
@@ -334,11 +339,11 @@ class Context:
     def last_stats(self):
         """dict of the last call's work: evaluations, table bytes, launches, rounds, configs,
         configurations kept as bitmaps"""
-        v = (C.c_int64 * 8)()
-        _check(lib().wse_last_stats(self._ctx, v, 8), self._ctx)
+        v = (C.c_int64 * 9)()
+        _check(lib().wse_last_stats(self._ctx, v, 9), self._ctx)
         return {"evals": v[0], "table_bytes": v[1], "eval_launches": v[2], "rounds": v[3],
                 "configs": v[4], "bitmap_configs": v[5], "lattice_bitmap_evals": v[6],
-                "lattice_bitmap_launches": v[7]}
+                "lattice_bitmap_launches": v[7], "row_range_units": v[8]}
 
     def last_evals(self, n):
         """address evaluations of each configuration of the last call"""
@@ -378,9 +383,9 @@ class Context:
 class Server:
     """Continuous-batching server of a context (include/wsest.h, serving)."""
 
-    def __init__(self, ctx, memory_budget_bytes=0, max_inflight=0, max_queue=0):
+    def __init__(self, ctx, memory_budget_bytes=0, max_inflight=0, max_queue=0, round_evals=0):
         self.ctx = ctx
-        o = wse_server_opts(int(memory_budget_bytes), int(max_inflight), int(max_queue))
+        o = wse_server_opts(int(memory_budget_bytes), int(max_inflight), int(max_queue), int(round_evals))
         self._srv = C.c_void_p()
         _check(lib().wse_server_start(ctx.handle, C.byref(o), C.byref(self._srv)), ctx.handle)
         self._pending = {}

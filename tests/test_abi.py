@@ -52,7 +52,7 @@ def test_status_strings(wlib):
     assert L.wse_status_str(-6) == b"not ready"
 
 
-def test_struct_sizes_match_the_header():
+def test_struct_sizes_match_the_header(tmp_path):
     from paper_2204_14242_amd import wsest
     src = r'''
 #include <stdio.h>
@@ -62,9 +62,8 @@ int main(void) {
          sizeof(wse_kernel_desc), sizeof(wse_hw), sizeof(wse_space), sizeof(wse_result));
   return 0;
 }'''
-    tmp = os.path.join(ROOT, "_work") if os.path.isdir(os.path.join(ROOT, "_work")) else "/tmp"
-    c_path = os.path.join(tmp, "abi_sizes.c")
-    exe = os.path.join(tmp, "abi_sizes")
+    c_path = str(tmp_path / "abi_sizes.c")
+    exe = str(tmp_path / "abi_sizes")
     open(c_path, "w").write(src)
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c_path, "-o", exe], check=True)
     sizes = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]

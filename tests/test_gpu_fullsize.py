@@ -140,8 +140,11 @@ def test_row_ranges_equal_enumeration_full_size(ctx):
         try:
             ctx.set_tuning(row_ranges=0)
             a, ra = ctx.estimate(spec, mode=wsest.BATCHED)
+            assert ctx.last_stats()["row_range_units"] == 0
             ctx.set_tuning(row_ranges=1)
             b, rb = ctx.estimate(spec, mode=wsest.BATCHED)
+            # the second estimate did fill its sets from row ranges
+            assert ctx.last_stats()["row_range_units"] > 0
         finally:
             ctx.set_tuning(**base)
         assert a.tobytes() == b.tobytes() and np.array_equal(ra, rb), wl

@@ -11,7 +11,7 @@ import pytest
 
 from paper_2204_14242_amd import workloads as W
 from gpu_common import assert_same, gpu_available, run_gpu, run_oracle
-from helpers import TINY_HW, with_hw
+from helpers import TINY_HW, load_expr, with_hw
 
 pytestmark = pytest.mark.gpu
 
@@ -64,9 +64,11 @@ def test_stencil_64_sample(ctx, orc):
     sp = dict(sp, domains=[(64, 64, 64)], explicit=list(range(0, 230, 7)))
     got = check(ctx, orc, [(k, hw, sp)], "stencil 64^3")
     # the representation asked for is the one that ran
-    n_bitmap = ctx.last_stats()["bitmap_configs"]
+    st = ctx.last_stats()
     n_ok = int((got["status"] == 0).sum())
-    assert n_bitmap == (0 if ctx.representation == "hash" else n_ok)
+    assert st["bitmap_configs"] == (0 if ctx.representation == "hash" else n_ok)
+    # row ranges ran exactly where asked for
+    assert (st["row_range_units"] > 0) == (ctx.representation == "rows")
 
 
 def test_stencil_folding_and_elements(ctx, orc):
@@ -150,6 +152,33 @@ def test_edge_cases(ctx, orc):
     assert (got["status"] == -1).any() and (got["status"] == 0).any()
 
 
+def range_kernel(align, sign=1, far=None):
+    # 8 B loads of element gid and stores of element gid + 1 (x only); with
+    # `far`, a second field aligned `far` bytes away takes the same accesses
+    fields = [(8, align)] + ([(8, align + far)] if far is not None else [])
+    ex = []
+    for f in range(len(fields)):
+        ex += [load_expr(f, cg=(sign, 0, 0)), load_expr(f, c0=1, cg=(sign, 0, 0), store=1)]
+    return W.affine_kernel(fields, ex)
+
+
+def test_address_range_edges(ctx, orc):
+    # addresses up to the representable limit of +-2^62 bytes, mixed with valid
+    # configurations: with one 64-thread block per wave, grids of 1..3 blocks
+    # never evaluate an address past the limit and a grid of 4 does
+    sp = W.affine_space([(1, 1, 1), (2, 1, 1), (3, 1, 1), (4, 1, 1)], min_threads=64, max_threads=64)
+    sp["bx_exps"], sp["by_exps"], sp["bz_exps"] = [6], [0], [0]
+    hw = with_hw(W.HW1, n_cu=1, blocks_per_cu=1)
+    lim = 1 << 62
+    specs = [(range_kernel(lim - 8 * 129), hw, sp),
+             (range_kernel(-lim + 8 * 127, sign=-1), hw, sp),
+             (range_kernel(1 << 61), hw, sp),                    # sector numbers past 2^47
+             (range_kernel(-(1 << 60), far=1 << 61), hw, sp)]   # two fields 2^61 bytes apart
+    got = check(ctx, orc, specs, "address range edges")
+    assert [int(v) for v in got["status"][:8]] == [0, 0, 0, -3] * 2
+    assert (got["status"][8:] == 0).all()
+
+
 def test_plain_equals_batched(ctx, orc):
     k, hw, sp = W.stencil_plain()
     sp = dict(sp, domains=[(64, 64, 64)], explicit=list(range(3, 230, 17)))
@@ -168,3 +197,38 @@ def test_stencil_plain_256_golden(ctx):
     say("case stencil 256^3 all 230 configs vs stored oracle values")
     got, rank = run_gpu(ctx, [(k, hw, sp)])
     assert_same(got, g["results"], rank, g["rank"], "stencil 256^3 golden")
+
+
+def test_multidim_address_space(ctx, orc):
+    # the wave and layer sets in the multi-dimensional address space
+    # (Sec. 4.4.1): stencils with folding, both element sizes, ghost layers
+    # and alignments, the LBM kernel, and the wrapped 100-wide access pair
+    specs = []
+    k = dict(W.star_stencil(4, align=40, ghost=3), address_space="multidim")
+    sp = W.lattice_space([(64, 64, 64), (100, 36, 20)], min_threads=32, max_threads=1024,
+                         fy=(1, 2, 4), fz=(1, 2), elems=[4, 8])
+    n = 2 * 2 * 2 * 3 * 251
+    sp["explicit"] = sorted(random.Random(41).sample(range(n), 48))
+    specs.append((k, W.HW1, sp))
+    kl = dict(W.lbm_two_phase(8), address_space="multidim")
+    spl = W.lattice_space([(40, 24, 16)], min_threads=32, max_threads=256, fy=(1, 2), fz=(1, 2), exps=range(7))
+    spl["explicit"] = list(range(0, 4 * 84, 29))
+    specs.append((kl, W.H2, spl))
+    kw = W.lattice_kernel_from([(0, 0, 100, 0, 0), (0, 0, 0, 1, 0), (1, 1, 0, 0, 0)], n_fields=2,
+                               address_space="multidim")
+    specs.append((kw, with_hw(W.HW1, n_cu=64, blocks_per_cu=1),
+                  W.lattice_space([(100, 20, 3)], min_threads=64, max_threads=256, exps=range(9))))
+    got = check(ctx, orc, specs, "multi-dimensional address space")
+    assert (got["status"] == 0).all()
+
+
+def test_layer_condition_scan_sample(ctx, orc):
+    # the constant-volume domain-size scan (Sec. 5.7): every block shape of at
+    # most 2 layers in z on two plane sizes, either side of the A100 L2's
+    # sequential layer condition (one z block layer stays cheap for the oracle)
+    k, hw, sp = W.layer_condition_scan(xy=(160, 448))
+    shapes = [(a, b, c) for a in range(11) for b in range(11) for c in range(11) if a + b + c == 10]
+    pick = [d * 66 + i for d in range(2) for i, s in enumerate(shapes) if s[2] <= 1]
+    sp["explicit"] = pick
+    got = check(ctx, orc, [(k, hw, sp)], "layer-condition scan")
+    assert (got["status"] == 0).all() and len(got) == len(pick)

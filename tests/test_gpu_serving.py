@@ -167,3 +167,34 @@ def test_invalid_request_is_rejected_at_submit(ctx):
         assert srv.wait(t, timeout_us=60_000_000)
     finally:
         srv.stop()
+
+
+def test_small_request_behind_a_large_one_finishes_first(ctx):
+    # Rounds take one configuration of each admitted request in turn and stop
+    # at an evaluation budget, so a small request submitted right after a large
+    # one joins the next short round and is done long before the large one.
+    from paper_2204_14242_amd import wsest
+    k, hw, sp = W.stencil_batched()
+    kid, hid = ctx.register_kernel(k), ctx.register_hw(hw)
+    n = ctx.space_size(kid, hid, sp)
+    per_domain = n // 5
+    # about 1,600 configurations of the 512^3 and 1024^3 domains: seconds of work
+    big = [(kid, hid, dict(sp, explicit=list(range(3 * per_domain, n, 10))))]
+    kp, hwp, spp = W.stencil_plain()
+    kpid, hpid = ctx.register_kernel(kp), ctx.register_hw(hwp)
+    small = [(kpid, hpid, dict(spp, domains=[(64, 64, 64)], explicit=list(range(0, 230, 23))))]
+    alone_small = ctx.estimate(small)
+    srv = wsest.Server(ctx, memory_budget_bytes=1 << 30, max_inflight=8, round_evals=1 << 36)
+    try:
+        say("case serving: small request behind a large one")
+        t_big = srv.submit(big, want_rank=False)
+        t_small = srv.submit(small)
+        assert srv.wait(t_small, timeout_us=120_000_000)
+        assert srv.wait(t_big, timeout_us=300_000_000)
+        _, _, done_big = srv.times(t_big)
+        _, _, done_small = srv.times(t_small)
+        assert done_small < done_big
+        res, rank = srv.result(t_small)
+        assert res.tobytes() == alone_small[0].tobytes() and np.array_equal(rank, alone_small[1])
+    finally:
+        srv.stop()
