@@ -234,6 +234,29 @@ wse_status wse_estimate(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces,
                         wse_result* out, int32_t* rank_out, int64_t out_capacity,
                         int32_t mode, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * estimate as wse_estimate(..., WSE_BATCHED, ...), byte-identical results
+ * and ranks, with no hipMalloc, hipFree or allocating library call.  All
+ * of its working memory (configuration records, folding expansions, work
+ * lists, the rounds' tables) lives in the library's scratch array: a
+ * static device array of 256 MiB that every GPU the library runs on holds
+ * until the process ends.  Rounds are launched directly, not replayed from
+ * captured graphs.  The kernel and hardware tables must be registered
+ * beforehand (registration allocates).
+ * Limits: the request's records (about 1.2 KiB per configuration, plus its
+ * spaces and folding expansions) must leave at least 16 MiB of the array
+ * for tables, else WSE_ENOMEM and nothing runs; a configuration whose
+ * tables exceed what is left gets status WSE_ENOMEM, as one exceeding the
+ * arena does in wse_estimate.  out/rank_out may be host or device memory.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (each call clears what must start at zero): calls that overlap on
+ * one GPU, from different contexts or threads, race and must not be made.
+ * Calls on one context are serialised by the context. */
+wse_status wse_estimate_noalloc(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces,
+                                wse_result* out, int32_t* rank_out, int64_t out_capacity,
+                                void* stream);
+
 /* ----------------------------------------------------------------- tuning */
 
 /* Launch and table-sizing parameters of the evaluation kernels.  They

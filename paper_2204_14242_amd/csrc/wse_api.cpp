@@ -56,7 +56,7 @@ static int64_t now_ns()
 namespace {
 
 // A device buffer that grows by reallocation, or a borrowed piece of memory
-// the library does not own, which
+// the library does not own (the no-allocation entry point's scratch), which
 // never grows and is never freed.
 template <typename T>
 struct DevBuf {
@@ -88,6 +88,28 @@ struct DevBuf {
         p = nullptr;
         cap = 0;
         owned = true;
+    }
+};
+
+// Consecutive 256-byte aligned pieces of one piece of device memory.  Once
+// a piece does not fit, every later take fails too (`failed`), so that no
+// piece is handed out after one that is missing.
+struct Carve {
+    char* base;
+    size_t cap, used = 0, wanted = 0;
+    bool failed = false;
+    template <typename T>
+    T* take(size_t n)
+    {
+        size_t off = (wanted + 255) & ~(size_t)255;
+        size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        wanted = off + bytes;
+        if (failed || off > cap || bytes > cap - off) {
+            failed = true;
+            return nullptr;
+        }
+        used = wanted;
+        return (T*)(base + off);
     }
 };
 
@@ -217,6 +239,7 @@ struct wse_ctx {
     int device = 0;
     char* arena = nullptr;
     size_t arena_bytes = 0;
+    char* scratch = nullptr;  // this device's scratch array (address from hipGetSymbolAddress)
     int n_cu = 256;
     size_t max_lds = 64 * 1024;  // LDS bytes one workgroup may allocate
     std::mutex mu;      // execution resources: arena, expansions, graphs, round buffers
@@ -318,7 +341,8 @@ wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out)
         delete c;
         return fail(WSE_ENOMEM, std::string("arena allocation failed: ") + hipGetErrorString(e));
     }
-    e = c->d_kernels.reserve(kMaxKernels);
+    e = scratch_address(device, &c->scratch);
+    if (e == hipSuccess) e = c->d_kernels.reserve(kMaxKernels);
     if (e == hipSuccess) e = c->d_hws.reserve(kMaxHws);
     if (e != hipSuccess) {
         c->d_kernels.release();
@@ -671,7 +695,7 @@ static DevTables dev_tables(wse_ctx* c, const SpaceDev* spaces, int n_spaces,
 }
 
 // Device memory one sequence of arena rounds runs in: the context's arena,
-// work list and round descriptor, or pieces of memory lent to one call.
+// work list and round descriptor, or pieces of the scratch array.
 struct RoundMem {
     char* arena;
     size_t arena_bytes;
@@ -1173,6 +1197,139 @@ extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t 
     j.rank_out = rank_out;
     wse_status s = estimate_job(c, j, ctx_round_mem(c), mode == WSE_BATCHED, mode == WSE_BATCHED,
                                 (hipStream_t)stream);
+    j.release();
+    return s;
+}
+
+// Work list entries per configuration and round: at most four evaluation
+// passes and five counted tables.
+constexpr size_t kWorkPerConfig = 9;
+// Work list capacity of the no-allocation entry point (entries per round).
+constexpr size_t kScratchWork = 9 * 2048;
+// The table area of the no-allocation entry point is at least this large.
+constexpr size_t kScratchMinTables = (size_t)16 << 20;
+
+extern "C" wse_status wse_estimate_noalloc(wse_ctx* c, const wse_space* spaces, int32_t n_spaces, wse_result* out,
+                                           int32_t* rank_out, int64_t out_capacity, void* stream)
+{
+    if (!c || (!spaces && n_spaces > 0) || n_spaces < 0) return fail(WSE_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_TRY(hipSetDevice(c->device));
+    if (!c->scratch) return fail(WSE_EDEVICE, "the scratch array has no device address");
+    hipStream_t st = (hipStream_t)stream;
+    Job j;
+    WSE_TRY(job_init(c, j, spaces, n_spaces));
+    if (j.total > out_capacity) return fail(WSE_EINVAL, "out_capacity is smaller than the number of configurations");
+    if (!out && j.total > 0) return fail(WSE_EINVAL, "out is null");
+    if (j.total == 0) return WSE_OK;
+    j.out = out;
+    j.rank_out = rank_out;
+    // the folding expansions this request needs, computed into the scratch
+    // array (the resident ones live in memory the context allocates)
+    std::vector<std::tuple<int, int, int>> keys;
+    for (auto& h : j.sp) {
+        if (h.dev.kind != WSE_KERNEL_LATTICE) continue;
+        for (int a = 0; a < h.dev.n_fy; a++)
+            for (int b = 0; b < h.dev.n_fz; b++) {
+                auto key = std::make_tuple((int)h.dev.kernel_id, (int)h.dev.fy[a], (int)h.dev.fz[b]);
+                auto it = std::find(keys.begin(), keys.end(), key);
+                h.dev.exp_id[a][b] = (int32_t)(it - keys.begin());
+                if (it == keys.end()) keys.push_back(key);
+            }
+    }
+    // carve the scratch array: request records, expansions, round memory;
+    // the rest holds the arena rounds' tables
+    const int ns = (int)j.sp.size();
+    size_t n_shapes = 0, n_outer = 0, n_expl = 0, n_exl = 0;
+    for (auto& h : j.sp) {
+        n_shapes += h.shapes.size();
+        n_outer += h.outer.size();
+        n_expl += h.expl.size();
+    }
+    std::vector<size_t> n_items(keys.size());
+    {
+        std::lock_guard<std::mutex> rk(c->reg_mu);
+        for (size_t q = 0; q < keys.size(); q++) {
+            n_items[q] = (size_t)c->kernels[std::get<0>(keys[q])].dev.n_items * std::get<1>(keys[q]) *
+                         std::get<2>(keys[q]);
+            n_exl += n_items[q];
+        }
+    }
+    const size_t n = (size_t)j.total;
+    Carve cv{c->scratch, kScratchBytes};
+    SpaceDev* p_sp = cv.take<SpaceDev>(ns);
+    int32_t* p_shapes = cv.take<int32_t>(n_shapes);
+    int32_t* p_outer = cv.take<int32_t>(n_outer);
+    int64_t* p_expl = cv.take<int64_t>(n_expl);
+    int64_t* p_first = cv.take<int64_t>(ns + 1);
+    int32_t* p_cfg_space = cv.take<int32_t>(n);
+    Cfg* p_cfgs = cv.take<Cfg>(n);
+    Counters* p_ctr = cv.take<Counters>(n);
+    Result* p_res = cv.take<Result>(n);
+    int32_t* p_rank = cv.take<int32_t>(n);
+    Expansion* p_exp = cv.take<Expansion>(keys.size());
+    ExpandJob* p_jobs = cv.take<ExpandJob>(keys.size());
+    ExprL* p_exl = cv.take<ExprL>(n_exl);
+    int32_t* p_keep = cv.take<int32_t>(n_exl);
+    RoundDesc* p_rd = cv.take<RoundDesc>(1);
+    WorkEntry* p_work = cv.take<WorkEntry>(kScratchWork);
+    char* p_arena = cv.take<char>(kScratchMinTables);
+    if (cv.failed || !p_arena)
+        return fail(WSE_ENOMEM, "request needs " + std::to_string(cv.wanted - kScratchMinTables) +
+                                    " bytes of scratch for its records and a 16 MiB table area beyond them; "
+                                    "the scratch array holds " + std::to_string(kScratchBytes) + " bytes");
+    const size_t arena_off = (size_t)(p_arena - c->scratch);
+    const size_t arena_bytes = (kScratchBytes - arena_off) & ~(size_t)255;
+    j.d_spaces.borrow(p_sp, ns);
+    j.d_shapes.borrow(p_shapes, std::max<size_t>(n_shapes, 1));
+    j.d_outer.borrow(p_outer, std::max<size_t>(n_outer, 1));
+    j.d_explicit.borrow(p_expl, std::max<size_t>(n_expl, 1));
+    j.d_space_first.borrow(p_first, ns + 1);
+    j.d_cfg_space.borrow(p_cfg_space, n);
+    j.d_cfgs.borrow(p_cfgs, n);
+    j.d_ctr.borrow(p_ctr, n);
+    j.d_res.borrow(p_res, n);
+    j.d_rank.borrow(p_rank, n);
+    DevBuf<WorkEntry> work;
+    work.borrow(p_work, kScratchWork);
+    wse_status s = WSE_OK;
+    if (!keys.empty()) {
+        std::vector<Expansion> host(keys.size());
+        std::vector<ExpandJob> jobs(keys.size());
+        size_t off = 0;
+        for (size_t q = 0; q < keys.size(); q++) {
+            host[q].ex = p_exl + off;
+            host[q].E = 0;
+            host[q].n_ld = 0;
+            jobs[q].kernel_id = std::get<0>(keys[q]);
+            jobs[q].fy = std::get<1>(keys[q]);
+            jobs[q].fz = std::get<2>(keys[q]);
+            jobs[q].pad = 0;
+            jobs[q].out = p_exl + off;
+            jobs[q].scratch_keep = p_keep + off;
+            jobs[q].slot = p_exp + q;
+            off += n_items[q];
+        }
+        s = sync_tables(c, st);
+        if (s == WSE_OK) {
+            hipError_t e = hipMemcpyAsync(p_exp, host.data(), host.size() * sizeof(Expansion),
+                                          hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(p_jobs, jobs.data(), jobs.size() * sizeof(ExpandJob), hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = launch_expand(p_jobs, (int)jobs.size(), dev_tables(c, nullptr, 0, p_exp), st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) s = fail(WSE_EDEVICE, std::string("expansion: ") + hipGetErrorString(e));
+        }
+        j.exp_tab = p_exp;
+    } else {
+        // affine kernels only: no expansion is read, the table is never empty
+        j.exp_tab = p_exp;
+    }
+    if (s == WSE_OK) {
+        RoundMem m{c->scratch + arena_off, arena_bytes, &work, p_rd, j.exp_tab, kScratchWork / kWorkPerConfig};
+        s = estimate_job(c, j, m, true, false, st);
+    }
+    work.release();
     j.release();
     return s;
 }

@@ -195,6 +195,13 @@ struct DevTables {
     int32_t n_spaces;
 };
 
+// Device memory of the entry point that allocates nothing: one static array
+// of kScratchBytes per device (wse_kernels.hip), held until the process ends.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+// Its address on `device`, which must be the current device: resolved once
+// per device with hipGetSymbolAddress (return code checked) and kept.
+hipError_t scratch_address(int device, char** ptr);
+
 // ---- launchers (wse_kernels.hip) ----
 struct ExpandJob {
     int32_t kernel_id, fy, fz, pad;

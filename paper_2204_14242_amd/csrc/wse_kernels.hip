@@ -22,6 +22,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 namespace wse {
@@ -2226,6 +2228,32 @@ hipError_t launch_rank(const Result* res, const int64_t* space_first, const int3
     hipLaunchKernelGGL(k_rank, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, res, space_first,
                        cfg_space, n, rank);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- scratch
+
+// Device memory of the entry point that allocates nothing.  Every GPU the
+// library runs on holds its own copy of this array until the process ends.
+// In host code the array's name is not a device address: host code uses only
+// the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, char** ptr)
+{
+    static std::mutex mu;
+    static std::map<int, char*> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = (char*)p;
+    *ptr = (char*)p;
+    return hipSuccess;
 }
 
 }  // namespace wse

@@ -110,6 +110,8 @@ def lib():
         L.wse_space_size.argtypes = [C.c_void_p, C.POINTER(wse_space), C.POINTER(C.c_int64)]
         L.wse_estimate.argtypes = [C.c_void_p, C.POINTER(wse_space), C.c_int32, C.c_void_p,
                                    C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+        L.wse_estimate_noalloc.argtypes = [C.c_void_p, C.POINTER(wse_space), C.c_int32, C.c_void_p,
+                                           C.c_void_p, C.c_int64, C.c_void_p]
         L.wse_last_timings.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32]
         L.wse_last_stats.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int32]
         L.wse_last_evals.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
@@ -128,7 +130,7 @@ def lib():
         L.wse_autotune.argtypes = [C.c_void_p, C.POINTER(wse_space), C.c_int32, C.c_int32,
                                    C.POINTER(wse_tuning)]
         for f in ("wse_ctx_create", "wse_kernel_register", "wse_hw_register", "wse_space_size",
-                  "wse_estimate", "wse_last_timings", "wse_rhat", "wse_last_stats",
+                  "wse_estimate", "wse_estimate_noalloc", "wse_last_timings", "wse_rhat", "wse_last_stats",
                   "wse_last_evals", "wse_server_start", "wse_submit", "wse_poll", "wse_wait",
                   "wse_ticket_times", "wse_server_stop", "wse_get_tuning", "wse_set_tuning",
                   "wse_autotune"):
@@ -298,6 +300,11 @@ class Context:
         device.  Returns (results, ranks)."""
         return self._estimate(specs, mode, out, rank, stream)
 
+    def estimate_noalloc(self, specs, out=None, rank=None, stream=None):
+        """The same estimate through wse_estimate_noalloc, which allocates no
+        device memory (its working memory is the library's scratch array)."""
+        return self._estimate(specs, None, out, rank, stream)
+
     def _estimate(self, specs, mode, out, rank, stream):
         keep = []
         arr = self.spaces_array(specs, keep)
@@ -319,8 +326,12 @@ class Context:
             rk = rank
             rank_ptr = rank.data_ptr()
         st = None if stream is None else C.c_void_p(int(stream))
-        _check(lib().wse_estimate(self._ctx, arr, len(specs), out_ptr, rank_ptr, n, int(mode), st),
-               self._ctx)
+        if mode is None:
+            _check(lib().wse_estimate_noalloc(self._ctx, arr, len(specs), out_ptr, rank_ptr, n, st),
+                   self._ctx)
+        else:
+            _check(lib().wse_estimate(self._ctx, arr, len(specs), out_ptr, rank_ptr, n, int(mode), st),
+                   self._ctx)
         if host_out:
             res = res[:n]
         if rank is None:
@@ -440,6 +451,7 @@ def exported_symbols():
     """Names the public header declares (checked by the CPU test suite)."""
     return ["wse_ctx_create", "wse_ctx_destroy", "wse_status_str", "wse_last_error",
             "wse_kernel_register", "wse_hw_register", "wse_space_size", "wse_estimate",
+            "wse_estimate_noalloc",
             "wse_rhat", "wse_last_timings", "wse_last_stats", "wse_last_evals",
             "wse_server_start", "wse_submit", "wse_poll", "wse_wait", "wse_ticket_times",
             "wse_server_stop", "wse_get_tuning", "wse_set_tuning", "wse_autotune"]
