@@ -32,6 +32,8 @@ RESULT_DTYPE = np.dtype([
     ("O_L", "<f8", 3), ("R_L", "<f8", 3), ("v_dram_ld", "<f8"), ("v_dram_st", "<f8"),
     ("bpl_l2", "<f8"), ("bpl_dram", "<f8"), ("p_l1", "<f8"), ("p_l2", "<f8"),
     ("p_dram", "<f8"), ("p_fp", "<f8"), ("perf", "<f8"),
+    ("O_L3", "<f8", 3), ("R_L3", "<f8", 3), ("O_W3", "<f8"), ("R_st3", "<f8"), ("v_l3_ld", "<f8"),
+    ("bpl_l3", "<f8"), ("p_l3", "<f8"),
 ])
 
 
@@ -61,7 +63,8 @@ class _Hw(C.Structure):
         "line_bytes", "sector_bytes", "warp_size", "l1_group_lanes", "l1_banks",
         "l1_bank_bytes", "l1_pair_bytes", "n_cu", "blocks_per_cu", "max_threads_per_cu",
         "l1_bytes", "l2_bytes")] + [(n, C.c_double) for n in (
-        "clock_hz", "bw_l2", "bw_dram", "flops_peak")] + [("fit", C.c_double * 12)]
+        "clock_hz", "bw_l2", "bw_dram", "flops_peak")] + [("fit", C.c_double * 12),
+                                                          ("l3_bytes", C.c_int64), ("bw_l3", C.c_double)]
 
 
 class _Space(C.Structure):
@@ -146,6 +149,8 @@ def _marshal(kernel, hw, space):
         for n in ("fit_l1", "fit_l2_y", "fit_l2_z", "fit_l2_store"):
             fit += list(hw[n])
         h.fit = (C.c_double * 12)(*fit)
+        h.l3_bytes = int(hw.get("l3_bytes", 0))
+        h.bw_l3 = float(hw.get("bw_l3", 0.0))
 
     s = _Space()
     s.n_bx, s.bx_exps = len(space["bx_exps"]), arr(space["bx_exps"])

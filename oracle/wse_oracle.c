@@ -903,6 +903,28 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
     v = v + (1.0 - r->R_st) * (double)(r->up_st_W - r->comp_st_W);
     r->v_dram_ld = v;
     r->v_dram_st = (double)r->comp_st_W;
+    r->p_l3 = INFINITY;
+    if (H->l3_bytes > 0) {
+        /* A third level below the L2 (the MI355X's Infinity Cache; the paper's
+         * outlook, Sec. 6, on deeper hierarchies): the same capacity-miss model
+         * once more, with the same hit-rate functions and the level's own
+         * capacity.  The L2 misses computed above become the L3's load
+         * traffic; what misses the L3 as well reaches DRAM. */
+        r->v_l3_ld = r->v_dram_ld;
+        for (int d = 0; d < 3; d++) {
+            if (sd[d] < 0) continue;
+            r->O_L3[d] = (double)(H->line_bytes * r->lines_L[d]) / (double)H->l3_bytes;
+            r->R_L3[d] = orc_rhat(d == 2 ? H->fit[2] : H->fit[1], r->O_L3[d]);
+        }
+        r->O_W3 = (double)(H->line_bytes * r->lines_W) / (double)H->l3_bytes;
+        r->R_st3 = orc_rhat(H->fit[3], r->O_W3);
+        double v3 = (double)new_sectors;
+        for (int d = 0; d < 3; d++) v3 = v3 + (1.0 - r->R_L3[d]) * (double)r->shell[d];
+        v3 = v3 + (1.0 - r->R_st3) * (double)(r->up_st_W - r->comp_st_W);
+        r->v_dram_ld = v3;
+        r->bpl_l3 = (double)H->sector_bytes * (r->v_l3_ld + r->v_dram_st) / (double)r->lups_W;
+        r->p_l3 = r->bpl_l3 > 0.0 ? H->bw_l3 / r->bpl_l3 : INFINITY;
+    }
 
     /* ---- four-limiter performance model (Sec. 2) ---- */
     double sector = (double)H->sector_bytes;
@@ -915,10 +937,13 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
     r->p_dram = r->bpl_dram > 0.0 ? H->bw_dram / r->bpl_dram : INFINITY;
     r->p_fp = (K->flops_per_lup > 0.0 && H->flops_peak > 0.0) ? H->flops_peak / K->flops_per_lup
                                                               : INFINITY;
-    double p[4] = {r->p_l1, r->p_l2, r->p_dram, r->p_fp};
-    int lim = 0;
-    for (int q = 1; q < 4; q++)
-        if (p[q] < p[lim]) lim = q;
+    /* the lowest limiter; ties go to the level nearest the registers:
+     * L1 (0), L2 (1), L3 (4), DRAM (2), then FP (3) */
+    const int order[5] = {0, 1, 4, 2, 3};
+    double p[5] = {r->p_l1, r->p_l2, r->p_dram, r->p_fp, r->p_l3};
+    int lim = order[0];
+    for (int q = 1; q < 5; q++)
+        if (p[order[q]] < p[lim]) lim = order[q];
     r->limiter = lim;
     r->perf = p[lim];
     r->status = ORC_OK;
@@ -967,6 +992,7 @@ static int hw_valid(const orc_hw* H)
     if (H->warp_size <= 0 || H->l1_group_lanes <= 0 || H->l1_banks <= 0) return 0;
     if (H->n_cu <= 0 || H->blocks_per_cu <= 0 || H->max_threads_per_cu <= 0) return 0;
     if (H->l1_bytes <= 0 || H->l2_bytes <= 0 || H->l1_pair_bytes <= 0) return 0;
+    if (H->l3_bytes < 0 || (H->l3_bytes > 0 && !(H->bw_l3 > 0.0))) return 0;
     return 1;
 }
 

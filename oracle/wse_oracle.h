@@ -64,6 +64,11 @@ typedef struct {
     int64_t l1_bytes, l2_bytes;
     double clock_hz, bw_l2, bw_dram, flops_peak;
     double fit[4][3];
+    /* optional third cache level between the L2 and DRAM (a memory-side cache
+     * shared by the whole device, such as an Infinity Cache): capacity in
+     * bytes (0 = none) and its bandwidth to the L2 in bytes/s */
+    int64_t l3_bytes;
+    double bw_l3;
 } orc_hw;
 
 /* Configuration space: value lists; canonical index is mixed radix over
@@ -95,6 +100,8 @@ typedef struct {
     int64_t s_layer[3], lines_L[3], shell[3];
     double O_l1, R_l1, v_l2l1_ld, O_W, R_st, O_L[3], R_L[3], v_dram_ld, v_dram_st;
     double bpl_l2, bpl_dram, p_l1, p_l2, p_dram, p_fp, perf;
+    /* third cache level (zero, and p_l3 = +inf, when the hardware has none) */
+    double O_L3[3], R_L3[3], O_W3, R_st3, v_l3_ld, bpl_l3, p_l3;
 } orc_result;
 
 int64_t orc_space_size(const orc_kernel* k, const orc_space* s);

@@ -52,7 +52,7 @@ def make_hw(*, warp_size, n_cu, l1_bytes, l2_bytes, clock_hz, bw_dram, bw_l2,
             l1_bank_bytes=8, l1_pair_bytes=1024, blocks_per_cu=2,
             max_threads_per_cu=2048, flops_peak=0.0,
             fit_l1=FIT_L1, fit_l2_y=FIT_L2_Y, fit_l2_z=FIT_L2_Z,
-            fit_l2_store=FIT_L2_STORE):
+            fit_l2_store=FIT_L2_STORE, l3_bytes=0, bw_l3=0.0):
     return dict(line_bytes=line_bytes, sector_bytes=sector_bytes,
                 warp_size=warp_size, l1_group_lanes=l1_group_lanes,
                 l1_banks=l1_banks, l1_bank_bytes=l1_bank_bytes,
@@ -62,7 +62,8 @@ def make_hw(*, warp_size, n_cu, l1_bytes, l2_bytes, clock_hz, bw_dram, bw_l2,
                 l2_bytes=l2_bytes, clock_hz=clock_hz, bw_l2=bw_l2,
                 bw_dram=bw_dram, flops_peak=flops_peak,
                 fit_l1=tuple(fit_l1), fit_l2_y=tuple(fit_l2_y),
-                fit_l2_z=tuple(fit_l2_z), fit_l2_store=tuple(fit_l2_store))
+                fit_l2_z=tuple(fit_l2_z), fit_l2_store=tuple(fit_l2_store),
+                l3_bytes=int(l3_bytes), bw_l3=float(bw_l3))
 
 
 # MI355X-shaped modelled GPU: 256 CUs, wave64, 2.4 GHz, 8 TB/s HBM; L1 and L2
@@ -77,6 +78,12 @@ H2 = make_hw(warp_size=32, n_cu=108, l1_bytes=192 * KIB, l2_bytes=20 * MIB,
              clock_hz=1.41e9, bw_dram=1400e9, bw_l2=5000e9)
 H3 = HW1
 HW_SETS = {"H1": H1, "H2": H2, "H3": H3}
+# The MI355X-shaped set with its memory-side Infinity Cache as a third level
+# (256 MiB; the 14.7 TB/s it is given to the L2s is a placeholder, as is the
+# 20 TB/s L2 bandwidth).  HW1's 4 MiB L2 is one XCD's: like the paper's split
+# A100 L2, the model assumes that lines used by CUs of several L2 sections are
+# duplicated in each, so one section's capacity is the effective one.
+HW1_L3 = dict(HW1, l3_bytes=256 * MIB, bw_l3=14.7e12)
 
 
 # --------------------------------------------------------------------------

@@ -744,3 +744,59 @@ def test_multidim_equals_linear_without_wraps(orc):
     a = one(orc, k, W.H2, sp)
     b = one(orc, md(k), W.H2, sp)
     assert a.tobytes() == b.tobytes()
+
+
+# --------------------------------------------------------------------------
+# a third cache level below the L2 (Sec. 6, Conclusion and Outlook: deeper
+# cache hierarchies; the MI355X's Infinity Cache)
+# --------------------------------------------------------------------------
+
+def test_third_level_absent_by_default(orc):
+    r = one(orc, W.star_stencil(4), W.HW1, single_lattice_space((64, 4, 4), (256, 256, 256)))
+    for key in ("O_L3", "R_L3", "O_W3", "R_st3", "v_l3_ld", "bpl_l3"):
+        assert (np.asarray(r[key]) == 0).all(), key
+    assert r["p_l3"] == np.inf and r["limiter"] != 4
+
+
+def test_third_level_takes_the_l2_misses(orc):
+    # the L2's misses are the L3's load traffic: with an L3, every L1 and L2
+    # term stays as it was and v_l3_ld is the DRAM load volume of the L2-only
+    # hierarchy; an L3 of the L2's size changes nothing below it
+    sp = single_lattice_space((32, 4, 8), (256, 256, 256))
+    hw108 = with_hw(W.HW1, n_cu=108)
+    a = one(orc, W.star_stencil(4), hw108, sp)
+    assert (a["shell"] > 0).sum() >= 2
+    b = one(orc, W.star_stencil(4), with_hw(hw108, l3_bytes=256 << 20, bw_l3=1e13), sp)
+    for key in ("v_l2l1_ld", "O_L", "R_L", "O_W", "R_st", "bpl_l2", "p_l1", "p_l2"):
+        assert np.array_equal(a[key], b[key]), key
+    assert b["v_l3_ld"] == a["v_dram_ld"]
+    # a larger capacity never misses more (the hit-rate functions fall with O)
+    assert b["v_dram_ld"] <= b["v_l3_ld"] and b["v_dram_ld"] < a["v_dram_ld"]
+    c = one(orc, W.star_stencil(4), with_hw(hw108, l3_bytes=hw108["l2_bytes"], bw_l3=1e13), sp)
+    assert c["v_dram_ld"] == c["v_l3_ld"] == a["v_dram_ld"]
+
+
+def test_third_level_limits(orc):
+    # R = 1 at the L3 (a = 1, b = 0): only compulsory sectors of the wave reach
+    # DRAM; R = 0: the L3 keeps nothing and DRAM sees the L2's misses
+    sp = single_lattice_space((64, 4, 4), (256, 256, 256))
+    keep = with_hw(W.HW1, l3_bytes=256 << 20, bw_l3=1e13, fit_l2_y=(1, 0, 0), fit_l2_z=(1, 0, 0),
+                   fit_l2_store=(1, 0, 0))
+    r = one(orc, W.star_stencil(4), keep, sp)
+    assert r["v_dram_ld"] == r["fpld_W"] - r["shell"].sum() == 131072
+    none = with_hw(W.HW1, l3_bytes=256 << 20, bw_l3=1e13, fit_l2_y=(0, 0, 0), fit_l2_z=(0, 0, 0),
+                   fit_l2_store=(0, 0, 0))
+    r = one(orc, W.star_stencil(4), none, sp)
+    assert r["v_dram_ld"] == r["v_l3_ld"] == r["fpld_W"] + r["up_st_W"] - r["comp_st_W"]
+
+
+def test_third_level_limiter(orc):
+    # 8 B/LUP of loads and 8 of stores between L2 and L3 (the (64,4,4) wave's
+    # full-plane volumes with every z overlap missing the L2): at 1 GB/s the
+    # L3 limits, and its bytes per LUP follow from the sector counts
+    sp = single_lattice_space((64, 4, 4), (256, 256, 256))
+    hw = with_hw(W.HW1, l3_bytes=256 << 20, bw_l3=1e9, fit_l2_z=(0, 0, 0))
+    r = one(orc, W.star_stencil(4), hw, sp)
+    assert r["limiter"] == 4 and r["perf"] == r["p_l3"]
+    assert r["bpl_l3"] == 32 * (r["v_l3_ld"] + r["v_dram_st"]) / r["lups_W"]
+    assert r["p_l3"] == 1e9 / r["bpl_l3"] and r["p_l3"] < min(r["p_l1"], r["p_l2"], r["p_dram"])
