@@ -151,6 +151,15 @@ typedef struct {
     int64_t l1_bytes, l2_bytes;  /* cache capacities */
     double clock_hz, bw_l2, bw_dram, flops_peak;   /* flops_peak 0 = FP limiter off */
     wse_fit fit_l1, fit_l2_y, fit_l2_z, fit_l2_store;   /* the x layer set uses fit_l2_y */
+    /* Optional third cache level between the L2 and DRAM, shared by the whole
+     * device (a memory-side cache such as the MI355X's Infinity Cache; the
+     * paper's outlook, Sec. 6, on deeper cache hierarchies): capacity in bytes
+     * (0 = no third level) and its bandwidth to the L2 in bytes/s (> 0 when
+     * l3_bytes > 0).  The capacity model of Sec. 4.5 is applied once more with
+     * the L2's hit-rate functions and this capacity: the L2 misses are the
+     * L3's load traffic (v_l3_ld) and what misses the L3 too is v_dram_ld. */
+    int64_t l3_bytes;
+    double bw_l3;
 } wse_hw;
 
 /* Register a hardware description; kept resident on the device. */
@@ -202,7 +211,7 @@ wse_status wse_space_size(wse_ctx* ctx, const wse_space* space, int64_t* n_confi
  *   bpl_*, p_l1, p_l2, p_dram, p_fp, perf, limiter (the lowest of four
  *     limiters): Sec. 2, "Performance Model", with Sec. 4.1 for p_fp. */
 typedef struct {
-    int32_t status, limiter;     /* limiter 0 L1, 1 L2, 2 DRAM, 3 FP; -1 on error */
+    int32_t status, limiter;     /* limiter 0 L1, 1 L2, 2 DRAM, 3 FP, 4 L3; -1 on error */
     int32_t shape[3], fold[3], domain[3], elem;   /* domain = grid for affine */
     int64_t index, n_expr;       /* canonical index; instructions per thread */
     int64_t lups_B, warps_B, l1_cycles_B, up_ld_B, up_st_B, comp_ld_B, lines_ld_B;
@@ -210,6 +219,10 @@ typedef struct {
     int64_t s_layer[3], lines_L[3], shell[3];
     double O_l1, R_l1, v_l2l1_ld, O_W, R_st, O_L[3], R_L[3], v_dram_ld, v_dram_st;
     double bpl_l2, bpl_dram, p_l1, p_l2, p_dram, p_fp, perf;   /* bytes/LUP, LUP/s */
+    /* third cache level (all 0 and p_l3 = +inf without one): O and R of the
+     * layer sets and of the wave against its capacity, its load volume from
+     * the L2 in sectors, its bytes per LUP and limiter */
+    double O_L3[3], R_L3[3], O_W3, R_st3, v_l3_ld, bpl_l3, p_l3;
 } wse_result;
 
 #define WSE_PLAIN 0    /* one launch sequence per configuration, host sync between */

@@ -536,6 +536,8 @@ wse_status wse_hw_register(wse_ctx* c, const wse_hw* h, int32_t* hw_id)
     if (!(h->clock_hz > 0 && h->bw_l2 > 0 && h->bw_dram > 0 && h->flops_peak >= 0))
         return fail(WSE_EINVAL, "clock and bandwidths must be positive");
     if (c->hws.size() >= kMaxHws) return fail(WSE_ENOMEM, "a context holds at most 4096 hardware sets");
+    if (h->l3_bytes < 0 || (h->l3_bytes > 0 && !(h->bw_l3 > 0)))
+        return fail(WSE_EINVAL, "l3_bytes must be >= 0, with bw_l3 > 0 when there is a third level");
     HwDev d;
     std::memset(&d, 0, sizeof(d));
     d.line_bytes = h->line_bytes;
@@ -561,6 +563,8 @@ wse_status wse_hw_register(wse_ctx* c, const wse_hw* h, int32_t* hw_id)
     d.bw_l2 = h->bw_l2;
     d.bw_dram = h->bw_dram;
     d.flops_peak = h->flops_peak;
+    d.l3_bytes = h->l3_bytes;
+    d.bw_l3 = h->l3_bytes > 0 ? h->bw_l3 : 0.0;
     for (int i = 0; i < 4; i++) {
         d.fit[i][0] = fits[i]->a;
         d.fit[i][1] = fits[i]->b;

@@ -81,6 +81,8 @@ struct HwDev {
     int64_t l1_bytes, l2_bytes;
     double clock_hz, bw_l2, bw_dram, flops_peak;
     double fit[4][3];
+    int64_t l3_bytes;  // third cache level (0 = none)
+    double bw_l3;
 };
 
 struct Expansion {
@@ -185,6 +187,7 @@ struct Result {  // identical layout to wse_result
     int64_t s_layer[3], lines_L[3], shell[3];
     double O_l1, R_l1, v_l2l1_ld, O_W, R_st, O_L[3], R_L[3], v_dram_ld, v_dram_st;
     double bpl_l2, bpl_dram, p_l1, p_l2, p_dram, p_fp, perf;
+    double O_L3[3], R_L3[3], O_W3, R_st3, v_l3_ld, bpl_l3, p_l3;
 };
 
 struct DevTables {

@@ -2157,9 +2157,30 @@ __global__ void k_reduce(const Cfg* cfgs, const Counters* ctr, int64_t n, DevTab
     v = v + (1.0 - r.R_st) * (double)(r.up_st_W - r.comp_st_W);
     r.v_dram_ld = v;
     r.v_dram_st = (double)r.comp_st_W;
-    // four limiters (Sec. 2)
-    double sector = (double)H.sector_bytes;
     const double inf = __builtin_inf();
+    r.p_l3 = inf;
+    if (H.l3_bytes > 0) {
+        // a third level below the L2 (a memory-side cache such as the
+        // Infinity Cache; Sec. 6 on deeper hierarchies): the L2's misses are
+        // its load traffic, and the capacity model with the L2's hit-rate
+        // functions and the L3's capacity gives what reaches DRAM
+        r.v_l3_ld = r.v_dram_ld;
+        for (int d = 0; d < 3; d++) {
+            if (c.s[d] < 0) continue;
+            r.O_L3[d] = (double)(H.line_bytes * r.lines_L[d]) / (double)H.l3_bytes;
+            r.R_L3[d] = dev_rhat(d == 2 ? H.fit[2] : H.fit[1], r.O_L3[d]);
+        }
+        r.O_W3 = (double)(H.line_bytes * r.lines_W) / (double)H.l3_bytes;
+        r.R_st3 = dev_rhat(H.fit[3], r.O_W3);
+        double v3 = (double)fresh;
+        for (int d = 0; d < 3; d++) v3 = v3 + (1.0 - r.R_L3[d]) * (double)r.shell[d];
+        v3 = v3 + (1.0 - r.R_st3) * (double)(r.up_st_W - r.comp_st_W);
+        r.v_dram_ld = v3;
+        r.bpl_l3 = (double)H.sector_bytes * (r.v_l3_ld + r.v_dram_st) / (double)r.lups_W;
+        r.p_l3 = r.bpl_l3 > 0.0 ? H.bw_l3 / r.bpl_l3 : inf;
+    }
+    // the limiters (Sec. 2)
+    double sector = (double)H.sector_bytes;
     r.bpl_l2 = sector * (r.v_l2l1_ld + (double)r.up_st_B) / (double)r.lups_B;
     r.bpl_dram = sector * (r.v_dram_ld + r.v_dram_st) / (double)r.lups_W;
     r.p_l1 = r.l1_cycles_B > 0 ? (double)r.lups_B * (double)H.n_cu * H.clock_hz / (double)r.l1_cycles_B
@@ -2167,10 +2188,13 @@ __global__ void k_reduce(const Cfg* cfgs, const Counters* ctr, int64_t n, DevTab
     r.p_l2 = r.bpl_l2 > 0.0 ? H.bw_l2 / r.bpl_l2 : inf;
     r.p_dram = r.bpl_dram > 0.0 ? H.bw_dram / r.bpl_dram : inf;
     r.p_fp = (K.flops_per_lup > 0.0 && H.flops_peak > 0.0) ? H.flops_peak / K.flops_per_lup : inf;
-    double p[4] = {r.p_l1, r.p_l2, r.p_dram, r.p_fp};
+    // the lowest; ties go to the level nearest the registers: L1 (0), L2 (1),
+    // L3 (4), DRAM (2), FP (3)
+    const double p[5] = {r.p_l1, r.p_l2, r.p_dram, r.p_fp, r.p_l3};
+    const int order[5] = {0, 1, 4, 2, 3};
     int lim = 0;
-    for (int q = 1; q < 4; q++)
-        if (p[q] < p[lim]) lim = q;
+    for (int q = 1; q < 5; q++)
+        if (p[order[q]] < p[lim]) lim = order[q];
     r.limiter = lim;
     r.perf = p[lim];
     r.status = 0;

@@ -31,8 +31,10 @@ RESULT_DTYPE = np.dtype([
     ("O_L", "<f8", 3), ("R_L", "<f8", 3), ("v_dram_ld", "<f8"), ("v_dram_st", "<f8"),
     ("bpl_l2", "<f8"), ("bpl_dram", "<f8"), ("p_l1", "<f8"), ("p_l2", "<f8"),
     ("p_dram", "<f8"), ("p_fp", "<f8"), ("perf", "<f8"),
+    ("O_L3", "<f8", 3), ("R_L3", "<f8", 3), ("O_W3", "<f8"), ("R_st3", "<f8"), ("v_l3_ld", "<f8"),
+    ("bpl_l3", "<f8"), ("p_l3", "<f8"),
 ])
-assert RESULT_DTYPE.itemsize == 400
+assert RESULT_DTYPE.itemsize == 488
 
 
 class wse_field(C.Structure):
@@ -65,7 +67,8 @@ class wse_hw(C.Structure):
         "l1_pair_bytes", "n_cu", "blocks_per_cu", "max_threads_per_cu")] + [
         ("l1_bytes", C.c_int64), ("l2_bytes", C.c_int64), ("clock_hz", C.c_double),
         ("bw_l2", C.c_double), ("bw_dram", C.c_double), ("flops_peak", C.c_double),
-        ("fit_l1", wse_fit), ("fit_l2_y", wse_fit), ("fit_l2_z", wse_fit), ("fit_l2_store", wse_fit)]
+        ("fit_l1", wse_fit), ("fit_l2_y", wse_fit), ("fit_l2_z", wse_fit), ("fit_l2_store", wse_fit),
+        ("l3_bytes", C.c_int64), ("bw_l3", C.c_double)]
 
 
 class wse_space(C.Structure):
@@ -175,6 +178,8 @@ def hw_struct(hw):
     for n in ("fit_l1", "fit_l2_y", "fit_l2_z", "fit_l2_store"):
         a, b, c = hw[n]
         setattr(h, n, wse_fit(a, b, c))
+    h.l3_bytes = int(hw.get("l3_bytes", 0))
+    h.bw_l3 = float(hw.get("bw_l3", 0.0))
     return h
 
 
@@ -296,7 +301,7 @@ class Context:
 
         specs: list of (kernel_id, hw_id, space_dict).  With out/rank None
         the results come back as host numpy arrays; torch CUDA tensors (uint8
-        of n*400 bytes, int32 of n) may be passed to keep results on the
+        of n*488 bytes, int32 of n) may be passed to keep results on the
         device.  Returns (results, ranks)."""
         return self._estimate(specs, mode, out, rank, stream)
 

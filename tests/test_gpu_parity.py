@@ -232,3 +232,19 @@ def test_layer_condition_scan_sample(ctx, orc):
     sp["explicit"] = pick
     got = check(ctx, orc, [(k, hw, sp)], "layer-condition scan")
     assert (got["status"] == 0).all() and len(got) == len(pick)
+
+
+def test_third_cache_level(ctx, orc):
+    # the MI355X-shaped hardware with its Infinity Cache as a third level, and
+    # an A100-shaped one with a small third level (both limit in places)
+    k = W.star_stencil(4)
+    sp = W.lattice_space([(64, 64, 64), (128, 128, 128)], min_threads=64, max_threads=1024,
+                         fy=(1, 2), fz=(1, 2), elems=[8])
+    sp["explicit"] = sorted(random.Random(47).sample(range(2 * 4 * 230), 24))
+    kl = W.lbm_two_phase(8)
+    spl = W.lattice_space([(48, 32, 24)], min_threads=64, max_threads=256, exps=range(7))
+    spl["explicit"] = list(range(0, 97, 3))
+    specs = [(k, W.HW1_L3, sp), (kl, with_hw(W.H2, l3_bytes=24 << 20, bw_l3=2e12), spl)]
+    got = check(ctx, orc, specs, "third cache level")
+    assert (got["status"] == 0).all() and (got["v_l3_ld"] > 0).all()
+    assert (got["limiter"] == 4).any() or (got["v_dram_ld"] < got["v_l3_ld"]).any()
