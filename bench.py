@@ -102,7 +102,7 @@ def parse():
                         "rate (0 = skip)")
     p.add_argument("--serve-fractions", default="0.3,0.6,0.9",
                    help="arrival rates of the served sweep, as fractions of the served capacity")
-    p.add_argument("--autotune-sample", type=int, default=0,
+    p.add_argument("--autotune-sample", type=int, default=256,
                    help="configurations of the workload the autotuner times (0 = hand-set defaults)")
     return p.parse_args()
 

@@ -199,7 +199,9 @@ struct Job {
     int32_t* rank_out = nullptr;
     DevBuf<SpaceDev> d_spaces;
     DevBuf<int32_t> d_shapes, d_outer, d_cfg_space, d_rank;
-    DevBuf<int64_t> d_explicit, d_space_first;
+    DevBuf<int64_t> d_explicit, d_space_first, d_chunk_first;
+    DevBuf<RankKey> d_sorted;
+    int64_t n_chunks = 0;           // ranking chunks over all spaces
     DevBuf<Cfg> d_cfgs;
     DevBuf<Counters> d_ctr;
     DevBuf<Result> d_res;
@@ -221,6 +223,8 @@ struct Job {
         d_rank.release();
         d_explicit.release();
         d_space_first.release();
+        d_chunk_first.release();
+        d_sorted.release();
         d_cfgs.release();
         d_ctr.release();
         d_res.release();
@@ -797,7 +801,7 @@ static wse_status job_init(wse_ctx* c, Job& j, const wse_space* spaces, int32_t 
         j.total += j.sp[i].n;
     }
     if (j.total > ((int64_t)1 << 31)) return fail(WSE_EINVAL, "too many configurations in one request");
-    size_t per = sizeof(Cfg) + sizeof(Counters) + sizeof(Result) + 2 * sizeof(int32_t);
+    size_t per = sizeof(Cfg) + sizeof(Counters) + sizeof(Result) + sizeof(RankKey) + 2 * sizeof(int32_t);
     j.mem_bytes = (size_t)j.total * per + 4096 * (size_t)(n_spaces + 1);
     for (auto& h : j.sp)
         j.mem_bytes += (h.shapes.size() + h.outer.size()) * 4 + h.expl.size() * 8 + sizeof(SpaceDev);
@@ -837,6 +841,12 @@ static wse_status job_prepare(wse_ctx* c, Job& j, hipStream_t st, size_t arena_b
         for (int64_t q = 0; q < j.sp[i].n; q++) cfg_space[j.sp[i].dev.first + q] = i;
     }
     first[n_spaces] = j.total;
+    // ranking chunks: every space's configurations in chunks of kRankChunk
+    std::vector<int64_t> chunk_first(n_spaces + 1);
+    chunk_first[0] = 0;
+    for (int i = 0; i < n_spaces; i++)
+        chunk_first[i + 1] = chunk_first[i] + (j.sp[i].n + kRankChunk - 1) / kRankChunk;
+    j.n_chunks = chunk_first[n_spaces];
     HIP_TRY(hipMemcpyAsync(j.d_shapes.p, shapes.data(), shapes.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(j.d_outer.p, outer.data(), outer.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     if (!expl.empty())
@@ -849,6 +859,10 @@ static wse_status job_prepare(wse_ctx* c, Job& j, hipStream_t st, size_t arena_b
     HIP_TRY(j.d_cfg_space.reserve(j.total));
     HIP_TRY(j.d_space_first.reserve(n_spaces + 1));
     HIP_TRY(hipMemcpyAsync(j.d_space_first.p, first.data(), first.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(j.d_chunk_first.reserve(n_spaces + 1));
+    HIP_TRY(hipMemcpyAsync(j.d_chunk_first.p, chunk_first.data(), chunk_first.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(j.d_sorted.reserve(j.total));
     HIP_TRY(hipMemcpyAsync(j.d_cfg_space.p, cfg_space.data(), j.total * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(launch_decode(j.d_cfgs.p, j.total, dev_tables(c, j.d_spaces.p, n_spaces, j.exp_tab),
                           c->table_slack, c->bitmap_log2, st));
@@ -887,7 +901,8 @@ static wse_status job_finish(wse_ctx* c, Job& j, hipStream_t st)
     if (j.rank_out) {
         bool rank_dev = is_device_ptr(j.rank_out);
         int32_t* rk = rank_dev ? j.rank_out : j.d_rank.p;
-        HIP_TRY(launch_rank(res, j.d_space_first.p, j.d_cfg_space.p, j.total, rk, st));
+        HIP_TRY(launch_rank(res, j.d_space_first.p, j.d_cfg_space.p, j.total, n_spaces, j.d_chunk_first.p,
+                            j.n_chunks, j.d_sorted.p, rk, st));
         if (!rank_dev) HIP_TRY(hipMemcpyAsync(j.rank_out, rk, j.total * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     }
     if (!out_dev) HIP_TRY(hipMemcpyAsync(j.out, res, j.total * sizeof(Result), hipMemcpyDeviceToHost, st));
@@ -1271,6 +1286,8 @@ extern "C" wse_status wse_estimate_noalloc(wse_ctx* c, const wse_space* spaces, 
     Counters* p_ctr = cv.take<Counters>(n);
     Result* p_res = cv.take<Result>(n);
     int32_t* p_rank = cv.take<int32_t>(n);
+    int64_t* p_chunk_first = cv.take<int64_t>(ns + 1);
+    RankKey* p_sorted = cv.take<RankKey>(n);
     Expansion* p_exp = cv.take<Expansion>(keys.size());
     ExpandJob* p_jobs = cv.take<ExpandJob>(keys.size());
     ExprL* p_exl = cv.take<ExprL>(n_exl);
@@ -1294,6 +1311,8 @@ extern "C" wse_status wse_estimate_noalloc(wse_ctx* c, const wse_space* spaces, 
     j.d_ctr.borrow(p_ctr, n);
     j.d_res.borrow(p_res, n);
     j.d_rank.borrow(p_rank, n);
+    j.d_chunk_first.borrow(p_chunk_first, ns + 1);
+    j.d_sorted.borrow(p_sorted, n);
     DevBuf<WorkEntry> work;
     work.borrow(p_work, kScratchWork);
     wse_status s = WSE_OK;

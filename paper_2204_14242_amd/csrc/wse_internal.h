@@ -227,7 +227,15 @@ hipError_t launch_count(const WorkEntry* work, const RoundDesc* rd, int64_t grou
 hipError_t launch_reduce(const Cfg* cfgs, const Counters* ctr, int64_t n, DevTables t,
                          Result* out, hipStream_t s);
 hipError_t launch_rhat(const double* fit, const double* O, double* R, int64_t n, hipStream_t s);
+// ranking: spaces cut into chunks of kRankChunk configurations, each sorted
+// in LDS; chunk_first[i] = first chunk of space i (n_spaces + 1 entries)
+constexpr int kRankChunk = 2048;
+struct RankKey {
+    double perf;
+    int64_t index;
+};
 hipError_t launch_rank(const Result* res, const int64_t* space_first, const int32_t* cfg_space,
-                       int64_t n, int32_t* rank, hipStream_t s);
+                       int64_t n, int32_t n_spaces, const int64_t* chunk_first, int64_t n_chunks,
+                       RankKey* sorted, int32_t* rank, hipStream_t s);
 
 }  // namespace wse

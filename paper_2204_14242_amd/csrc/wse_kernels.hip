@@ -2228,29 +2228,106 @@ hipError_t launch_rhat(const double* fit, const double* O, double* R, int64_t n,
 
 // ------------------------------------------------------------------- rank
 
-__global__ void k_rank(const Result* res, const int64_t* space_first, const int32_t* cfg_space,
-                       int64_t n, int32_t* rank)
+// Rank of every configuration within its space: perf descending, then
+// canonical index ascending.  Each space is cut into chunks of kRankChunk
+// configurations; a workgroup sorts one chunk in LDS (bitonic network), so a
+// configuration's rank is its place in its own chunk plus, for every other
+// chunk of its space, the number of that chunk's keys before it (a binary
+// search in the sorted chunk): O(n log n) work for spaces of one chunk and
+// O(n (n / kRankChunk) log kRankChunk) beyond.
+__device__ __forceinline__ bool rank_before(const RankKey& a, const RankKey& b)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    return a.perf > b.perf || (a.perf == b.perf && a.index < b.index);
+}
+
+__global__ __launch_bounds__(256) void k_rank_sort(const Result* res, const int64_t* space_first,
+                                                   int32_t n_spaces, const int64_t* chunk_first,
+                                                   RankKey* sorted, int32_t* rank)
+{
+    // the space of this chunk: the last whose first chunk is at or before it
+    const int64_t ch = blockIdx.x;
+    int lo = 0, hi = n_spaces - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (chunk_first[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t c0 = space_first[lo] + (ch - chunk_first[lo]) * kRankChunk;
+    const int64_t left = space_first[lo + 1] - c0;
+    const int n = (int)(left < kRankChunk ? left : kRankChunk);
+    __shared__ RankKey key[kRankChunk];
+    __shared__ int16_t pos[kRankChunk];
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    for (int i = (int)threadIdx.x; i < np2; i += (int)blockDim.x) {
+        if (i < n) {
+            key[i].perf = res[c0 + i].perf;
+            key[i].index = res[c0 + i].index;
+        } else {
+            key[i].perf = -__builtin_inf();  // padding: after every real key
+            key[i].index = INT64_MAX;
+        }
+        pos[i] = (int16_t)i;
+    }
+    __syncthreads();
+    for (int k = 2; k <= np2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = (int)threadIdx.x; i < np2; i += (int)blockDim.x) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const RankKey a = key[i], b = key[p];
+                    const bool swap = (i & k) == 0 ? rank_before(b, a) : rank_before(a, b);
+                    if (swap) {
+                        key[i] = b;
+                        key[p] = a;
+                        const int16_t t = pos[i];
+                        pos[i] = pos[p];
+                        pos[p] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
+        sorted[c0 + i] = key[i];
+        rank[c0 + pos[i]] = i;  // place in its own chunk
+    }
+}
+
+__global__ void k_rank_merge(const Result* res, const int64_t* space_first, const int32_t* cfg_space,
+                             const RankKey* sorted, int64_t n, int32_t* rank)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int sp = cfg_space[i];
-    int64_t lo = space_first[sp], hi = space_first[sp + 1];
-    double p = res[i].perf;
-    int64_t idx = res[i].index;
-    int64_t r = 0;
-    for (int64_t j = lo; j < hi; j++) {
-        double q = res[j].perf;
-        r += (q > p) || (q == p && res[j].index < idx);
+    const int sp = cfg_space[i];
+    const int64_t s0 = space_first[sp], s1 = space_first[sp + 1];
+    if (s1 - s0 <= kRankChunk) return;  // one chunk: its place is its rank
+    const RankKey me = {res[i].perf, res[i].index};
+    const int64_t own = s0 + (i - s0) / kRankChunk * kRankChunk;
+    int64_t r = rank[i];
+    for (int64_t c0 = s0; c0 < s1; c0 += kRankChunk) {
+        if (c0 == own) continue;
+        const int64_t nc = s1 - c0 < kRankChunk ? s1 - c0 : kRankChunk;
+        int64_t a = 0, b = nc;  // keys of the chunk before `me` are a prefix of it
+        while (a < b) {
+            const int64_t m = (a + b) / 2;
+            if (rank_before(sorted[c0 + m], me)) a = m + 1;
+            else b = m;
+        }
+        r += a;
     }
     rank[i] = (int32_t)r;
 }
 
 hipError_t launch_rank(const Result* res, const int64_t* space_first, const int32_t* cfg_space,
-                       int64_t n, int32_t* rank, hipStream_t s)
+                       int64_t n, int32_t n_spaces, const int64_t* chunk_first, int64_t n_chunks,
+                       RankKey* sorted, int32_t* rank, hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rank, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, res, space_first,
-                       cfg_space, n, rank);
+    if (n == 0 || n_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rank_sort, dim3((unsigned)n_chunks), dim3(256), 0, s, res, space_first, n_spaces,
+                       chunk_first, sorted, rank);
+    hipLaunchKernelGGL(k_rank_merge, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, res, space_first,
+                       cfg_space, sorted, n, rank);
     return hipGetLastError();
 }
 

@@ -32,3 +32,20 @@ def test_traffic_only_for_the_profiled_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("stencil_plain") is None       # another workload
     source.write_bytes(b"__global__ void k() { /* changed */ }\n")
     assert bench.measured_traffic("stencil_batched") is None     # the kernel changed since
+
+
+def test_cpu_baseline_follows_the_cost_strata():
+    # the CPU-baseline leg on a small space: every stratum the budget affords
+    # is sampled, and the reported rate covers the whole space
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    from paper_2204_14242_amd import workloads as W
+    k, hw, sp = W.stencil_plain()
+    sp = dict(sp, domains=[(32, 32, 32)])
+    n = 230
+    evals = np.array([4 ** (5 + i % 4) for i in range(n)], dtype=np.float64)
+    out = bench.cpu_baseline(k, hw, sp, evals, budget_s=2.0)
+    assert out["kind"] == "oracle" and out["unit"] == "configs/s" and out["value"] > 0
+    assert 1 <= out["cores"] <= 16 and out["cores"] <= out["nproc"]
+    assert "4 cost strata" in out["sample"]

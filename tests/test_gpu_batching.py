@@ -132,3 +132,22 @@ def test_invalid_tuning_is_rejected(small_ctx):
         small_ctx.set_tuning(bitmap_log2=9)
     with pytest.raises(wsest.WseError):
         small_ctx.set_tuning(row_ranges=2)
+
+
+def test_rank_of_spaces_larger_than_a_chunk(small_ctx, orc):
+    # Ranks come from sorting chunks of 2,048 configurations and counting the
+    # keys of the other chunks before each one: a space of 8,032 cheap
+    # configurations (four chunks, only a few dozen distinct perf values, so
+    # that most order is decided by the canonical index) and a 2,048 one (one
+    # full chunk) in one call, against the oracle's ranks.
+    k = W.star_stencil(2)
+    big = W.lattice_space([(16, 16, 16)], min_threads=32, max_threads=1024, fy=(1, 2, 4, 8),
+                          fz=(1, 2, 4, 8), elems=[4, 8])
+    one_chunk = dict(big, explicit=list(range(0, 8032, 4))[:2048])
+    specs = [(k, W.H2, big), (k, W.H2, one_chunk)]
+    say("case ranks of spaces of 8,032 and 2,048 configurations")
+    got, grank = small_ctx.estimate([(small_ctx.register_kernel(k), small_ctx.register_hw(W.H2), sp)
+                                     for _, _, sp in specs])
+    want, wrank = run_oracle(orc, specs)
+    assert len(set(want["perf"].tolist())) < 200
+    assert_same(got, want, grank, wrank, "ranks across chunks")

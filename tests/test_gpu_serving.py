@@ -98,7 +98,7 @@ def test_memory_budget_serialises_admission(ctx):
     reqs = request_mix(12, 6, size=20)
     specs = register_all(ctx, reqs)
     alone = [ctx.estimate(s) for s in specs]
-    # every request needs about 20 * 1.2 KB + 8 KB of device records: the
+    # every request needs about 20 * 1.3 KB + 8 KB of device records: the
     # budget holds one of them, never two
     budget = 48 * 1024
     srv = wsest.Server(ctx, memory_budget_bytes=budget, max_inflight=8)
