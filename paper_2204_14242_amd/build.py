@@ -18,17 +18,27 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
 
-def build(verbose=False):
+# measurement kernels of the hit-rate fits (fit/star_probe.hip)
+PROBE_SRC = os.path.join(HERE, "fit", "star_probe.hip")
+PROBE_LIB = os.path.join(HERE, "fit", "libstarprobe.so")
+
+
+def _hipcc(sources, out, includes, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *FLAGS, *[a for inc in includes for a in ("-I", inc)], *sources, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
     if verbose and (r.stdout or r.stderr):
         print(r.stdout + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose=False):
+    _hipcc([os.path.join(CSRC, s) for s in SOURCES], LIB, [os.path.join(ROOT, "include"), CSRC], verbose)
+    _hipcc([PROBE_SRC], PROBE_LIB, [], verbose)
     return LIB
 
 
