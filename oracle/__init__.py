@@ -64,7 +64,8 @@ class _Hw(C.Structure):
         "l1_bank_bytes", "l1_pair_bytes", "n_cu", "blocks_per_cu", "max_threads_per_cu",
         "l1_bytes", "l2_bytes")] + [(n, C.c_double) for n in (
         "clock_hz", "bw_l2", "bw_dram", "flops_peak")] + [("fit", C.c_double * 12),
-                                                          ("l3_bytes", C.c_int64), ("bw_l3", C.c_double)]
+                                                          ("l3_bytes", C.c_int64), ("bw_l3", C.c_double),
+                                                          ("l2_sections", C.c_int64)]
 
 
 class _Space(C.Structure):
@@ -151,6 +152,7 @@ def _marshal(kernel, hw, space):
         h.fit = (C.c_double * 12)(*fit)
         h.l3_bytes = int(hw.get("l3_bytes", 0))
         h.bw_l3 = float(hw.get("bw_l3", 0.0))
+        h.l2_sections = int(hw.get("l2_sections", 1))
 
     s = _Space()
     s.n_bx, s.bx_exps = len(space["bx_exps"]), arr(space["bx_exps"])

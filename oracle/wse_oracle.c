@@ -759,11 +759,17 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
         fset_free(&lin);
     }
 
-    /* ---- wave footprint (Sec. 4.4) ---- */
+    /* ---- wave footprint (Sec. 4.4) ----
+     * With an L2 of several sections, every section caches the data of its
+     * own blocks: the wave and layer sets are kept per (field, section), set
+     * f + n_fields * (k mod sections) for block k, and a count is the sum over
+     * the sections (a unit two sections use is fetched by both). */
+    const int64_t nsec = H->l2_sections > 1 ? H->l2_sections : 1;
+    const int64_t nf = K->n_fields;
     fset fpld, fpst, lw;
-    fset_init(&fpld, K->n_fields);
-    fset_init(&fpst, K->n_fields);
-    fset_init(&lw, K->n_fields);
+    fset_init(&fpld, nf * nsec);
+    fset_init(&fpst, nf * nsec);
+    fset_init(&lw, nf * nsec);
     int64_t lanes_W = 0;
     warpstats wsw;
     memset(&wsw, 0, sizeof(wsw));
@@ -772,9 +778,10 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
         for (int64_t t = 0; t < c.P; t++) {
             if (!thread_at(&c, k, t, bid, tid)) continue;
             lanes_W++;
+            const int64_t fo = nf * (k % nsec);
             for (int64_t e = 0; e < c.nE; e++) {
-                fset_add(c.ex[e].st ? &fpst : &fpld, c.ex[e].f, wave_unit(&c, &c.ex[e], bid, tid, 0), 0);
-                fset_add(&lw, c.ex[e].f, wave_unit(&c, &c.ex[e], bid, tid, 1), 0);
+                fset_add(c.ex[e].st ? &fpst : &fpld, c.ex[e].f + fo, wave_unit(&c, &c.ex[e], bid, tid, 0), 0);
+                fset_add(&lw, c.ex[e].f + fo, wave_unit(&c, &c.ex[e], bid, tid, 1), 0);
             }
         }
     }
@@ -813,15 +820,15 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
          * every sector of a field, restricted to the key range of the wave's
          * load footprint in that field (nothing outside it can be a wave
          * sector) */
-        const int64_t nf = K->n_fields;
+        const int64_t nfs = nf * nsec;
         fset ll, ls;
-        fset_init(&ll, nf);
-        fset_init(&ls, nf);
+        fset_init(&ll, nfs);
+        fset_init(&ls, nfs);
         for (int64_t k = smin; k < w0; k++)
             for (int64_t t = 0; t < c.P; t++) {
                 if (!thread_at(&c, k, t, bid, tid)) continue;
                 for (int64_t e = 0; e < c.nE; e++) {
-                    const int64_t f = c.ex[e].f;
+                    const int64_t f = c.ex[e].f + nf * (k % nsec);
                     fset_add(&ll, f, wave_unit(&c, &c.ex[e], bid, tid, 1), k);
                     const kset* fp = &fpld.f[f];
                     uint64_t ks = unit_key(wave_unit(&c, &c.ex[e], bid, tid, 0));
@@ -829,14 +836,14 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
                         kset_add(&ls.f[f], ks, k);
                 }
             }
-        for (int64_t f = 0; f < nf; f++) {
+        for (int64_t f = 0; f < nfs; f++) {
             kset_compact(&ll.f[f]);
             kset_compact(&ls.f[f]);
         }
         for (int d = 0; d < 3; d++) {
             if (sd[d] < 0) continue;
             int64_t cnt = 0;
-            for (int64_t f = 0; f < nf; f++)
+            for (int64_t f = 0; f < nfs; f++)
                 for (int64_t q = 0; q < ll.f[f].n; q++) cnt += ll.f[f].a[q].tag >= sd[d];
             r->lines_L[d] = cnt;
         }
@@ -851,7 +858,7 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
                     ord[a] = ord[b2];
                     ord[b2] = t;
                 }
-        for (int64_t f = 0; f < nf; f++) {
+        for (int64_t f = 0; f < nfs; f++) {
             const kset* fp = &fpld.f[f];
             const kset* lf = &ls.f[f];
             /* latest layer block touching each wave load sector of the field, or -1 */
@@ -890,13 +897,16 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
     r->R_l1 = orc_rhat(H->fit[0], r->O_l1);
     r->v_l2l1_ld = (double)r->comp_ld_B + (1.0 - r->R_l1) * (double)(r->up_ld_B - r->comp_ld_B);
     int64_t new_sectors = r->fpld_W;
+    /* a sectioned L2: the sections are alike, each holding 1/sections of the
+     * summed allocation in its own capacity */
+    const int64_t l2_all = nsec * H->l2_bytes;
     for (int d = 0; d < 3; d++) {
         if (sd[d] < 0) continue;
-        r->O_L[d] = (double)(H->line_bytes * r->lines_L[d]) / (double)H->l2_bytes;
+        r->O_L[d] = (double)(H->line_bytes * r->lines_L[d]) / (double)l2_all;
         r->R_L[d] = orc_rhat(d == 2 ? H->fit[2] : H->fit[1], r->O_L[d]);
         new_sectors -= r->shell[d];
     }
-    r->O_W = (double)(H->line_bytes * r->lines_W) / (double)H->l2_bytes;
+    r->O_W = (double)(H->line_bytes * r->lines_W) / (double)l2_all;
     r->R_st = orc_rhat(H->fit[3], r->O_W);
     double v = (double)new_sectors;
     for (int d = 0; d < 3; d++) v = v + (1.0 - r->R_L[d]) * (double)r->shell[d];
@@ -993,6 +1003,7 @@ static int hw_valid(const orc_hw* H)
     if (H->n_cu <= 0 || H->blocks_per_cu <= 0 || H->max_threads_per_cu <= 0) return 0;
     if (H->l1_bytes <= 0 || H->l2_bytes <= 0 || H->l1_pair_bytes <= 0) return 0;
     if (H->l3_bytes < 0 || (H->l3_bytes > 0 && !(H->bw_l3 > 0.0))) return 0;
+    if (H->l2_sections < 0 || H->l2_sections > 64) return 0;
     return 1;
 }
 

@@ -69,6 +69,10 @@ typedef struct {
      * bytes (0 = none) and its bandwidth to the L2 in bytes/s */
     int64_t l3_bytes;
     double bw_l3;
+    /* L2 split into sections (the MI355X's eight XCD L2s; the A100's two
+     * halves, Sec. 3): block k runs on the CUs of section k mod l2_sections
+     * and its wave and layer data are cached there; 0 or 1 = one L2 */
+    int64_t l2_sections;
 } orc_hw;
 
 /* Configuration space: value lists; canonical index is mixed radix over

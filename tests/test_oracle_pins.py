@@ -800,3 +800,81 @@ def test_third_level_limiter(orc):
     assert r["limiter"] == 4 and r["perf"] == r["p_l3"]
     assert r["bpl_l3"] == 32 * (r["v_l3_ld"] + r["v_dram_st"]) / r["lups_W"]
     assert r["p_l3"] == 1e9 / r["bpl_l3"] and r["p_l3"] < min(r["p_l1"], r["p_l2"], r["p_dram"])
+
+
+# --------------------------------------------------------------------------
+# an L2 split into sections (Sec. 3: the A100's two L2 halves duplicate
+# data; Sec. 6, Conclusion and Outlook: the cache-line duplication that
+# lowers the effective capacity).  Block k caches in section k mod S.
+# --------------------------------------------------------------------------
+
+def test_sections_default_is_one_l2(orc):
+    sp = single_lattice_space((32, 4, 8), (256, 256, 256))
+    hw108 = with_hw(W.HW1, n_cu=108)
+    a = one(orc, W.star_stencil(4), hw108, sp)
+    for s in (0, 1):
+        b = one(orc, W.star_stencil(4), with_hw(hw108, l2_sections=s), sp)
+        assert a.tobytes() == b.tobytes()
+
+
+def test_far_apart_blocks_sum_their_footprints(orc):
+    # 64 sections for the (64,2,1) one-plane wave on 256^3: section k mod 64
+    # holds one x chunk of row pairs 32 rows apart, farther than the range-4
+    # halo reaches, so its blocks share nothing and the wave's counts are 512
+    # times those of one block (Sec. 4.3 closed forms)
+    sp = single_lattice_space((64, 2, 1), (256, 256, 256), elem=8)
+    r = one(orc, W.star_stencil(4), with_hw(W.HW1, l2_sections=64), sp)
+    assert r["blocks_W"] == 512
+    assert r["fpld_W"] == 512 * star_block_sectors(64, 2, 1) == 512 * 420
+    assert r["comp_st_W"] == 512 * 2 * 16
+    assert r["lines_W"] == 512 * (star_block_lines(64, 2, 1) + 2 * 4)
+
+
+def test_eight_sections_of_a_plane_wave_closed_form(orc):
+    # (64,2,1) blocks on 256^3 (no ghost layer, so halos wrap into the
+    # neighbouring row or plane): the one-plane wave's block k sits at
+    # x chunk k mod 4 and row pair (k / 4) mod 128, so section k mod 8 holds
+    # one 64-wide x chunk of every other row pair.  Counted by hand per
+    # section: 9 planes of its 128 rows (16 sectors each), the other 128 rows
+    # of the centre plane (y neighbours), 2 wrapped rows of a neighbouring
+    # plane, and one x-halo sector on each side of its 128 centre rows.
+    sp = single_lattice_space((64, 2, 1), (256, 256, 256), elem=8)
+    one_l2 = one(orc, W.star_stencil(4), W.HW1, sp)
+    r = one(orc, W.star_stencil(4), with_hw(W.HW1, l2_sections=8), sp)
+    per_section = 9 * 128 * 16 + 128 * 16 + 2 * 16 + 2 * 128
+    assert one_l2["fpld_W"] == 9 * 16384
+    assert r["fpld_W"] == 8 * per_section == 166144
+    assert r["comp_st_W"] == one_l2["comp_st_W"] == 16384      # stores never overlap
+    # lines (4 per 64-wide chunk): loads as above, plus the stored chunk rows
+    lines = 9 * 128 * 4 + 128 * 4 + 2 * 4 + 2 * 128 + 128 * 4
+    assert r["lines_W"] == 8 * lines
+    # the z layer set is the previous plane's wave: the same shape one plane down
+    assert r["s_layer"][2] == one_l2["s_layer"][2]
+    assert r["lines_L"][2] == 8 * lines
+    assert r["O_L"][2] == 128.0 * 8 * lines / (8 * 4 * 1024 * 1024)
+    # wave sectors the previous plane's section also loaded: its 8 shared
+    # source planes, plus 2 wrapped rows per section
+    assert r["shell"][2] == 8 * (8 * 128 * 16 + 2 * 16)
+    assert r["O_W"] == 128.0 * r["lines_W"] / (8 * 4 * 1024 * 1024)
+
+
+def test_sections_leave_disjoint_blocks_alone(orc):
+    # a copy kernel's blocks share no data: every count is the one-L2 count,
+    # only the occupancies divide by the number of sections
+    k = W.lattice_kernel_from([(0, 0, 0, 0, 0), (1, 1, 0, 0, 0)], n_fields=2)
+    sp = single_lattice_space((64, 4, 1), (256, 256, 64))
+    hw = with_hw(W.HW1, n_cu=64)
+    a = one(orc, k, hw, sp)
+    b = one(orc, k, with_hw(hw, l2_sections=4), sp)
+    assert (a["s_layer"] >= 0).any()
+    for key in ("fpld_W", "comp_st_W", "lines_W", "up_st_W", "lines_L", "shell", "s_layer"):
+        assert np.array_equal(a[key], b[key]), key
+    assert b["O_W"] == a["O_W"] / 4
+    assert np.array_equal(b["O_L"], a["O_L"] / 4)
+
+
+def test_sections_are_validated(orc):
+    sp = single_lattice_space((64, 2, 1), (64, 64, 64))
+    for bad in (-1, 65):
+        with pytest.raises(Exception):
+            orc.estimate(W.star_stencil(4), with_hw(W.HW1, l2_sections=bad), sp, n_threads=1)
