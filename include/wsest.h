@@ -160,6 +160,14 @@ typedef struct {
      * L3's load traffic (v_l3_ld) and what misses the L3 too is v_dram_ld. */
     int64_t l3_bytes;
     double bw_l3;
+    /* An L2 split into sections (the MI355X's eight XCD L2s; the A100's two
+     * halves, Sec. 3), 0 or 1 = one L2, at most 64.  Thread block k runs on
+     * the compute units of section k mod l2_sections and its data are cached
+     * there: the wave and layer sets are counted per section and summed, so
+     * a unit two sections use counts twice (the cache-line duplication of
+     * Sec. 6), and the occupancies O_W and O_L divide by l2_sections *
+     * l2_bytes.  The block's own footprint (L1) is not affected. */
+    int64_t l2_sections;
 } wse_hw;
 
 /* Register a hardware description; kept resident on the device. */

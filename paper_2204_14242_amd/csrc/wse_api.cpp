@@ -542,6 +542,7 @@ wse_status wse_hw_register(wse_ctx* c, const wse_hw* h, int32_t* hw_id)
     if (c->hws.size() >= kMaxHws) return fail(WSE_ENOMEM, "a context holds at most 4096 hardware sets");
     if (h->l3_bytes < 0 || (h->l3_bytes > 0 && !(h->bw_l3 > 0)))
         return fail(WSE_EINVAL, "l3_bytes must be >= 0, with bw_l3 > 0 when there is a third level");
+    if (h->l2_sections < 0 || h->l2_sections > 64) return fail(WSE_EINVAL, "l2_sections must be in [0, 64]");
     HwDev d;
     std::memset(&d, 0, sizeof(d));
     d.line_bytes = h->line_bytes;
@@ -569,6 +570,7 @@ wse_status wse_hw_register(wse_ctx* c, const wse_hw* h, int32_t* hw_id)
     d.flops_peak = h->flops_peak;
     d.l3_bytes = h->l3_bytes;
     d.bw_l3 = h->l3_bytes > 0 ? h->bw_l3 : 0.0;
+    d.l2_sections = h->l2_sections > 1 ? h->l2_sections : 1;
     for (int i = 0; i < 4; i++) {
         d.fit[i][0] = fits[i]->a;
         d.fit[i][1] = fits[i]->b;

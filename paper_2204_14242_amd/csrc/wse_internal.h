@@ -83,6 +83,7 @@ struct HwDev {
     double fit[4][3];
     int64_t l3_bytes;  // third cache level (0 = none)
     double bw_l3;
+    int64_t l2_sections;  // L2 sections, >= 1; block k caches in section k mod l2_sections
 };
 
 struct Expansion {
@@ -126,7 +127,7 @@ struct Cfg {
     // multi-dimensional address space, every array row on a line boundary of
     // its own, rows wsy elements apart, planes wsz, all fields based at wabase
     int64_t wsy, wsz, wabase;
-    int32_t multidim, pad3;
+    int32_t multidim, nsec;    // nsec: the hardware's L2 sections (>= 1)
     int64_t evals[3];           // thread x instruction evaluations per pass (upper bound)
     int64_t l_units;            // layer pass: segments of its blocks' threads in row order
     int64_t w_units;            // wave pass: segments of its blocks' threads in row order

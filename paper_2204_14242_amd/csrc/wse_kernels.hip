@@ -440,6 +440,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
     c.kernel_id = S.kernel_id;
     c.hw_id = S.hw_id;
     c.kind = S.kind;
+    c.nsec = H.l2_sections > 1 ? (int32_t)H.l2_sections : 1;
     c.expansion_id = -1;
     c.smin = -1;
     for (int d = 0; d < 3; d++) c.s[d] = -1;
@@ -483,7 +484,8 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         c.E = X.E;
         c.n_ld = X.n_ld;
         c.uniform_elem = c.elem ? c.elem : K.uniform_elem;
-        c.row_ok = c.uniform_elem > 0 && c.uniform_elem <= H.sector_bytes;
+        // (row ranges span blocks of several L2 sections: one L2 only)
+        c.row_ok = c.uniform_elem > 0 && c.uniform_elem <= H.sector_bytes && H.l2_sections <= 1;
         c.wsy = c.sy;
         c.wsz = c.sz;
         c.wabase = 0;
@@ -653,8 +655,10 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         if (bad) break;
         T.umin = umin;
         T.span = umax - umin + 1;
-        uint64_t keys = (uint64_t)K.n_fields * (uint64_t)T.span;
-        if (T.span <= 0 || keys / (uint64_t)K.n_fields != (uint64_t)T.span ||
+        // wave and layer sets: n_fields * span keys per L2 section
+        const uint64_t per = q >= T_WSEC ? (uint64_t)K.n_fields * (uint64_t)c.nsec : (uint64_t)K.n_fields;
+        uint64_t keys = per * (uint64_t)T.span;
+        if (T.span <= 0 || keys / per != (uint64_t)T.span ||
             bits_for(keys) + T.pb > 64) {
             bad = 1;
             break;
@@ -683,7 +687,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         const int lr = H.log2_line - H.log2_sector;
         const TableDesc& L = c.tab[T_WLINE];
         if (!bad && dense_g[1] && keys_of[T_WSEC] > 0 && keys_of[T_WLINE] > 0 && lr >= 0 && lr <= 5) {
-            const uint64_t keys = (uint64_t)K.n_fields * ((uint64_t)L.span << lr);
+            const uint64_t keys = (uint64_t)K.n_fields * (uint64_t)c.nsec * ((uint64_t)L.span << lr);
             if (keys < ((uint64_t)1 << 32)) {
                 c.tab[T_WSEC].umin = L.umin * ((int64_t)1 << lr);
                 c.tab[T_WSEC].span = L.span << lr;
@@ -1483,6 +1487,11 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     const uint32_t words_s = (uint32_t)TS.words, words_l = (uint32_t)TL.words;
     // wave pass on bitmaps whose lines follow from its sectors: no line probes
     const bool w_lines = !(PASS == PASS_W && DENSE && (c.dense & 4));
+    // an L2 of several sections: the wave and layer keys of block k lie in
+    // key block k mod nsec (n_fields * span keys each)
+    const int nsec = ROW ? c.nsec : 1;
+    const int64_t sec_keys_s = ROW ? (int64_t)P.K->n_fields * span_s : 0;
+    const int64_t sec_keys_l = ROW ? (int64_t)P.K->n_fields * span_l : 0;
     // wave and layer passes: row order of their blocks; layer band
     // thresholds in recency order
     RowOrder ro;
@@ -1507,6 +1516,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             if (DENSE && !seg_ok) break;
             int64_t tx, ty, tz, gx, gy, gz, kcur, bcur[3];
             int64_t seg_x0 = 0;
+            int64_t soff_s = 0, soff_l = 0;  // this lane's section key offsets
             bool valid;
             if (ROW) {
                 // row order: 64 consecutive x of one thread row
@@ -1522,6 +1532,11 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 tx = gx & (b0 - 1);
                 kcur = bcur[0] + nb0 * r;
                 valid = seg_ok && gx < xe && gy < T1 && gz < T2;
+                if (nsec > 1) {
+                    const int64_t sec = kcur % nsec;
+                    soff_s = sec * sec_keys_s;
+                    soff_l = sec * sec_keys_l;
+                }
             } else {
                 const int64_t t = (int64_t)sgi * kLanes + lane;
                 const bool inb = t < Pthr;
@@ -1586,7 +1601,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             // step form one range.  Such segments (on one layer band) take the
             // run-end word probes; the instruction loop is instantiated for
             // both kinds of segment.
-            bool seg_runs = RUNS && KIND == 0 && ROW && uelem > 0 && uelem <= ((int64_t)1 << ls);
+            bool seg_runs = RUNS && KIND == 0 && ROW && uelem > 0 && uelem <= ((int64_t)1 << ls) && nsec == 1;
             if (RUNS && DENSE && PASS == PASS_L)
                 seg_runs = seg_runs &&
                            __ballot(valid && band != (uint32_t)__builtin_amdgcn_readfirstlane((int)band)) == 0;
@@ -1652,8 +1667,9 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                         }
                         bool act = valid && ok;
                         if (DENSE) {
-                            const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
-                            const uint32_t kl = (uint32_t)(ul + readlane64(ic.fl, q) - 1);
+                            // (the run-end modes hold one section only)
+                            const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1 + (FAST ? 0 : soff_s));
+                            const uint32_t kl = (uint32_t)(ul + readlane64(ic.fl, q) - 1 + (FAST ? 0 : soff_l));
                             WordProbe a, b = {0ull, 0u, 0u, 0u, false};
                             if (FAST) {
                                 // every valid key is in range unless the item
@@ -1669,8 +1685,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                             word_commit(P, b);
                         } else {
                             uint64_t ks =
-                                act ? (((uint64_t)(us + readlane64(ic.fs, q)) << 2) | (st ? 2u : 1u)) : 0;
-                            uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q)) : 0;
+                                act ? (((uint64_t)(us + readlane64(ic.fs, q) + soff_s) << 2) | (st ? 2u : 1u)) : 0;
+                            uint64_t kl = act ? (uint64_t)(ul + readlane64(ic.fl, q) + soff_l) : 0;
                             new0 = lds_add(P, P.set0, ks, sec_pb, sec_mode);
                             new1 = lds_add(P, P.set1, kl, line_pb, line_mode);
                         }
@@ -1687,8 +1703,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                             // address, shifted with the table offsets folded in)
                             const uint32_t kl =
                                 MODE == 3 ? (uint32_t)(((uint64_t)ubase + (uint64_t)readlane64((int64_t)ic.SL, q)) >> ll)
-                                          : (uint32_t)(ul + readlane64(ic.fl, q) - 1);
-                            const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1);
+                                          : (uint32_t)(ul + readlane64(ic.fl, q) - 1 + (FAST ? 0 : soff_l));
+                            const uint32_t ks = (uint32_t)(us + readlane64(ic.fs, q) - 1 + (FAST ? 0 : soff_s));
                             WordProbe a = {0ull, 0u, 0u, 0u, false}, b;
                             if (FAST) {
                                 if (MODE == 3) {
@@ -1715,13 +1731,13 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                             word_commit(P, a);
                         } else {
                             uint64_t kl = (valid && ok)
-                                              ? ((((uint64_t)(ul + readlane64(ic.fl, q))) << line_pb) | tag)
+                                              ? ((((uint64_t)(ul + readlane64(ic.fl, q) + soff_l)) << line_pb) | tag)
                                               : 0;
                             new1 = lds_add(P, P.set1, kl, line_pb, line_mode);
                             if (do_sec) {
                                 bool in = valid && (uint64_t)us < (uint64_t)span_s;
                                 uint64_t ks =
-                                    in ? ((((uint64_t)(us + readlane64(ic.fs, q))) << sec_pb) | tag) : 0;
+                                    in ? ((((uint64_t)(us + readlane64(ic.fs, q) + soff_s)) << sec_pb) | tag) : 0;
                                 new0 = lds_add(P, P.set0, ks, sec_pb, sec_mode);
                             }
                         }
@@ -2144,13 +2160,15 @@ __global__ void k_reduce(const Cfg* cfgs, const Counters* ctr, int64_t n, DevTab
     r.R_l1 = dev_rhat(H.fit[0], r.O_l1);
     r.v_l2l1_ld = (double)r.comp_ld_B + (1.0 - r.R_l1) * (double)(r.up_ld_B - r.comp_ld_B);
     int64_t fresh = r.fpld_W;
+    // a sectioned L2: the summed allocation against the sections' capacity
+    const double l2_all = (double)(H.l2_sections * H.l2_bytes);
     for (int d = 0; d < 3; d++) {
         if (c.s[d] < 0) continue;
-        r.O_L[d] = (double)(H.line_bytes * r.lines_L[d]) / (double)H.l2_bytes;
+        r.O_L[d] = (double)(H.line_bytes * r.lines_L[d]) / l2_all;
         r.R_L[d] = dev_rhat(d == 2 ? H.fit[2] : H.fit[1], r.O_L[d]);
         fresh -= r.shell[d];
     }
-    r.O_W = (double)(H.line_bytes * r.lines_W) / (double)H.l2_bytes;
+    r.O_W = (double)(H.line_bytes * r.lines_W) / l2_all;
     r.R_st = dev_rhat(H.fit[3], r.O_W);
     double v = (double)fresh;
     for (int d = 0; d < 3; d++) v = v + (1.0 - r.R_L[d]) * (double)r.shell[d];

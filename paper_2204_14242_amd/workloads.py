@@ -52,7 +52,7 @@ def make_hw(*, warp_size, n_cu, l1_bytes, l2_bytes, clock_hz, bw_dram, bw_l2,
             l1_bank_bytes=8, l1_pair_bytes=1024, blocks_per_cu=2,
             max_threads_per_cu=2048, flops_peak=0.0,
             fit_l1=FIT_L1, fit_l2_y=FIT_L2_Y, fit_l2_z=FIT_L2_Z,
-            fit_l2_store=FIT_L2_STORE, l3_bytes=0, bw_l3=0.0):
+            fit_l2_store=FIT_L2_STORE, l3_bytes=0, bw_l3=0.0, l2_sections=1):
     return dict(line_bytes=line_bytes, sector_bytes=sector_bytes,
                 warp_size=warp_size, l1_group_lanes=l1_group_lanes,
                 l1_banks=l1_banks, l1_bank_bytes=l1_bank_bytes,
@@ -63,7 +63,8 @@ def make_hw(*, warp_size, n_cu, l1_bytes, l2_bytes, clock_hz, bw_dram, bw_l2,
                 bw_dram=bw_dram, flops_peak=flops_peak,
                 fit_l1=tuple(fit_l1), fit_l2_y=tuple(fit_l2_y),
                 fit_l2_z=tuple(fit_l2_z), fit_l2_store=tuple(fit_l2_store),
-                l3_bytes=int(l3_bytes), bw_l3=float(bw_l3))
+                l3_bytes=int(l3_bytes), bw_l3=float(bw_l3),
+                l2_sections=int(l2_sections))
 
 
 # MI355X-shaped modelled GPU: 256 CUs, wave64, 2.4 GHz, 8 TB/s HBM; L1 and L2

@@ -68,7 +68,7 @@ class wse_hw(C.Structure):
         ("l1_bytes", C.c_int64), ("l2_bytes", C.c_int64), ("clock_hz", C.c_double),
         ("bw_l2", C.c_double), ("bw_dram", C.c_double), ("flops_peak", C.c_double),
         ("fit_l1", wse_fit), ("fit_l2_y", wse_fit), ("fit_l2_z", wse_fit), ("fit_l2_store", wse_fit),
-        ("l3_bytes", C.c_int64), ("bw_l3", C.c_double)]
+        ("l3_bytes", C.c_int64), ("bw_l3", C.c_double), ("l2_sections", C.c_int64)]
 
 
 class wse_space(C.Structure):
@@ -180,6 +180,7 @@ def hw_struct(hw):
         setattr(h, n, wse_fit(a, b, c))
     h.l3_bytes = int(hw.get("l3_bytes", 0))
     h.bw_l3 = float(hw.get("bw_l3", 0.0))
+    h.l2_sections = int(hw.get("l2_sections", 1))
     return h
 
 

@@ -248,3 +248,36 @@ def test_third_cache_level(ctx, orc):
     got = check(ctx, orc, specs, "third cache level")
     assert (got["status"] == 0).all() and (got["v_l3_ld"] > 0).all()
     assert (got["limiter"] == 4).any() or (got["v_dram_ld"] < got["v_l3_ld"]).any()
+
+
+def test_l2_sections(ctx, orc):
+    # an L2 split into sections (the MI355X's eight XCD L2s, the A100's two
+    # halves): stencils on both element sizes with folding, the LBM kernel,
+    # random affine kernels on a non-power-of-two section count, and the
+    # multi-dimensional address space
+    k = W.star_stencil(4)
+    sp = W.lattice_space([(64, 64, 64), (128, 128, 128)], min_threads=64, max_threads=1024,
+                         fy=(1, 2), fz=(1, 2), elems=[4, 8])
+    sp["explicit"] = sorted(random.Random(53).sample(range(2 * 2 * 4 * 230), 24))
+    kl = W.lbm_two_phase(8)
+    spl = W.lattice_space([(48, 32, 24)], min_threads=64, max_threads=256, exps=range(7))
+    spl["explicit"] = list(range(1, 97, 4))
+    specs = [(k, with_hw(W.HW_MI355X, l2_sections=8), sp), (kl, with_hw(W.H2, l2_sections=2), spl)]
+    for seed in range(3):
+        rng = random.Random(700 + seed)
+        nf = rng.randint(1, 3)
+        fields = [(8, rng.choice([0, 24, -64])) for _ in range(nf)]
+        exprs = [(rng.randrange(nf), int(rng.random() < 0.3), rng.randint(-20, 20),
+                  *[rng.randint(-3, 3) * m for m in (1, 37, 900)],
+                  *[rng.randint(-3, 3) * m for m in (1, 37, 900)],
+                  *[rng.randint(-1, 1) * m for m in (1, 37, 900)]) for _ in range(rng.randint(2, 7))]
+        hw = with_hw(TINY_HW, warp_size=8, n_cu=rng.randint(2, 5), l2_sections=3)
+        spa = W.affine_space([(rng.randint(2, 6), rng.randint(2, 4), rng.randint(1, 3))],
+                             min_threads=2, max_threads=64, exps=range(5))
+        specs.append((W.affine_kernel(fields, exprs), hw, spa))
+    km = dict(W.star_stencil(2, ghost=2), address_space="multidim")
+    spm = W.lattice_space([(60, 36, 20)], min_threads=32, max_threads=512, fy=(1, 2), elems=[8])
+    spm["explicit"] = list(range(0, 2 * 185, 9))
+    specs.append((km, with_hw(W.HW1, n_cu=64, l2_sections=4), spm))
+    got = check(ctx, orc, specs, "L2 sections")
+    assert (got["status"] == 0).sum() >= len(got) - 4
