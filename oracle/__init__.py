@@ -33,7 +33,7 @@ RESULT_DTYPE = np.dtype([
     ("bpl_l2", "<f8"), ("bpl_dram", "<f8"), ("p_l1", "<f8"), ("p_l2", "<f8"),
     ("p_dram", "<f8"), ("p_fp", "<f8"), ("perf", "<f8"),
     ("O_L3", "<f8", 3), ("R_L3", "<f8", 3), ("O_W3", "<f8"), ("R_st3", "<f8"), ("v_l3_ld", "<f8"),
-    ("bpl_l3", "<f8"), ("p_l3", "<f8"),
+    ("bpl_l3", "<f8"), ("p_l3", "<f8"), ("pages_W", "<i8"),
 ])
 
 
@@ -65,7 +65,7 @@ class _Hw(C.Structure):
         "l1_bytes", "l2_bytes")] + [(n, C.c_double) for n in (
         "clock_hz", "bw_l2", "bw_dram", "flops_peak")] + [("fit", C.c_double * 12),
                                                           ("l3_bytes", C.c_int64), ("bw_l3", C.c_double),
-                                                          ("l2_sections", C.c_int64)]
+                                                          ("l2_sections", C.c_int64), ("page_bytes", C.c_int64)]
 
 
 class _Space(C.Structure):
@@ -153,6 +153,7 @@ def _marshal(kernel, hw, space):
         h.l3_bytes = int(hw.get("l3_bytes", 0))
         h.bw_l3 = float(hw.get("bw_l3", 0.0))
         h.l2_sections = int(hw.get("l2_sections", 1))
+        h.page_bytes = int(hw.get("page_bytes", 0))
 
     s = _Space()
     s.n_bx, s.bx_exps = len(space["bx_exps"]), arr(space["bx_exps"])

@@ -250,7 +250,7 @@ typedef struct {
      * the number of rows (y values) per plane, and per granularity (0 sector,
      * 1 line) the smallest x unit and the number of x units per row */
     int md;
-    int64_t md_lo[3], md_ny, md_xu_lo[2], md_nxu[2];
+    int64_t md_lo[3], md_ny, md_xu_lo[3], md_nxu[3];
 } cfg;
 
 static int64_t floor_div(int64_t a, int64_t b)
@@ -305,7 +305,7 @@ static int64_t addr_of(cfg* c, const expr* e, const int64_t* bid, const int64_t*
  * numbers and the field's alignment plays no part. */
 static int64_t wave_unit(cfg* c, const expr* e, const int64_t* bid, const int64_t* tid, int gi)
 {
-    const int64_t gran = gi == 0 ? c->H->sector_bytes : c->H->line_bytes;
+    const int64_t gran = gi == 0 ? c->H->sector_bytes : (gi == 1 ? c->H->line_bytes : c->H->page_bytes);
     if (!c->md) return floor_div(addr_of(c, e, bid, tid), gran);
     int64_t gid[3];
     for (int d = 0; d < 3; d++) gid[d] = bid[d] * c->b[d] + tid[d];
@@ -720,8 +720,9 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
             hi[d] = c.g + c.fold[d] * (c.T[d] - 1) + vhi[d];
         }
         c.md_ny = hi[1] - c.md_lo[1] + 1;
-        for (int gi = 0; gi < 2; gi++) {
-            const int64_t gran = gi == 0 ? H->sector_bytes : H->line_bytes;
+        for (int gi = 0; gi < 3; gi++) {
+            const int64_t gran = gi == 0 ? H->sector_bytes : (gi == 1 ? H->line_bytes : H->page_bytes);
+            if (gran <= 0) continue;
             c.md_xu_lo[gi] = floor_div(c.md_lo[0] * elem, gran);
             c.md_nxu[gi] = floor_div(hi[0] * elem, gran) - c.md_xu_lo[gi] + 1;
         }
@@ -766,10 +767,13 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
      * the sections (a unit two sections use is fetched by both). */
     const int64_t nsec = H->l2_sections > 1 ? H->l2_sections : 1;
     const int64_t nf = K->n_fields;
-    fset fpld, fpst, lw;
+    fset fpld, fpst, lw, pg;
     fset_init(&fpld, nf * nsec);
     fset_init(&fpst, nf * nsec);
     fset_init(&lw, nf * nsec);
+    /* pages: one set per field for the whole wave (the translation of a page
+     * is needed once however many blocks or sections use it) */
+    fset_init(&pg, nf);
     int64_t lanes_W = 0;
     warpstats wsw;
     memset(&wsw, 0, sizeof(wsw));
@@ -782,6 +786,7 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
             for (int64_t e = 0; e < c.nE; e++) {
                 fset_add(c.ex[e].st ? &fpst : &fpld, c.ex[e].f + fo, wave_unit(&c, &c.ex[e], bid, tid, 0), 0);
                 fset_add(&lw, c.ex[e].f + fo, wave_unit(&c, &c.ex[e], bid, tid, 1), 0);
+                if (H->page_bytes > 0) fset_add(&pg, c.ex[e].f, wave_unit(&c, &c.ex[e], bid, tid, 2), 0);
             }
         }
     }
@@ -791,8 +796,10 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
     r->comp_st_W = fset_size(&fpst);
     r->lines_W = fset_size(&lw);
     r->up_st_W = wsw.up_st;
+    r->pages_W = H->page_bytes > 0 ? fset_size(&pg) : 0;
     fset_free(&fpst);
     fset_free(&lw);
+    fset_free(&pg);
 
     /* ---- layer-condition thread sets (Sec. 4.4.2) ----
      * C_d = { block(t - e_d) : t valid in the wave, t_d >= 1, block < w0 };
@@ -1004,6 +1011,10 @@ static int hw_valid(const orc_hw* H)
     if (H->l1_bytes <= 0 || H->l2_bytes <= 0 || H->l1_pair_bytes <= 0) return 0;
     if (H->l3_bytes < 0 || (H->l3_bytes > 0 && !(H->bw_l3 > 0.0))) return 0;
     if (H->l2_sections < 0 || H->l2_sections > 64) return 0;
+    if (H->page_bytes < 0 || (H->page_bytes > 0 && (H->page_bytes < H->line_bytes ||
+                                                    (H->page_bytes & (H->page_bytes - 1)) ||
+                                                    H->page_bytes > ((int64_t)1 << 30))))
+        return 0;
     return 1;
 }
 

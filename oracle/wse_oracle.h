@@ -73,6 +73,10 @@ typedef struct {
      * halves, Sec. 3): block k runs on the CUs of section k mod l2_sections
      * and its wave and layer data are cached there; 0 or 1 = one L2 */
     int64_t l2_sections;
+    /* translation page size in bytes for the count of pages the wave touches
+     * (Sec. 6, Conclusion and Outlook: TLB pages accessed by the current
+     * wave); 0 = not counted */
+    int64_t page_bytes;
 } orc_hw;
 
 /* Configuration space: value lists; canonical index is mixed radix over
@@ -106,6 +110,9 @@ typedef struct {
     double bpl_l2, bpl_dram, p_l1, p_l2, p_dram, p_fp, perf;
     /* third cache level (zero, and p_l3 = +inf, when the hardware has none) */
     double O_L3[3], R_L3[3], O_W3, R_st3, v_l3_ld, bpl_l3, p_l3;
+    /* distinct (field, page) pairs of the wave's loads and stores (0 when
+     * pages are not counted) */
+    int64_t pages_W;
 } orc_result;
 
 int64_t orc_space_size(const orc_kernel* k, const orc_space* s);

@@ -878,3 +878,68 @@ def test_sections_are_validated(orc):
     for bad in (-1, 65):
         with pytest.raises(Exception):
             orc.estimate(W.star_stencil(4), with_hw(W.HW1, l2_sections=bad), sp, n_threads=1)
+
+
+# --------------------------------------------------------------------------
+# translation pages touched by the wave (Sec. 6, Conclusion and Outlook: the
+# program metric of a TLB model is the pages accessed by the current wave)
+# --------------------------------------------------------------------------
+
+def test_pages_of_a_plane_wave_closed_form(orc):
+    # the (64,2,1) one-plane wave on 256^3 (middle wave: plane z = 128) loads
+    # the 9 planes z-4..z+4 of src and stores one plane of dst, each plane
+    # 512 KiB: 9 * 128 + 128 pages of 4 KiB; of 2 MiB pages, src bytes
+    # [62 MiB, 66.5 MiB) touch 3 and the dst plane [64, 64.5) MiB one
+    sp = single_lattice_space((64, 2, 1), (256, 256, 256), elem=8)
+    assert one(orc, W.star_stencil(4), W.HW1, sp)["pages_W"] == 0
+    r = one(orc, W.star_stencil(4), with_hw(W.HW1, page_bytes=4096), sp)
+    assert r["pages_W"] == 9 * 128 + 128 == 1280
+    r = one(orc, W.star_stencil(4), with_hw(W.HW1, page_bytes=2 << 20), sp)
+    assert r["pages_W"] == 3 + 1
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_line_sized_pages_are_the_wave_lines(orc, seed):
+    # a page of one line is a line: the count is the wave's line count of one
+    # L2, also when the L2 is sectioned (pages are counted for the whole wave)
+    k, sp = random_affine(seed), tiny_space(seed)
+    hw = with_hw(TINY_HW, page_bytes=TINY_HW["line_bytes"])
+    r, _ = orc.estimate(k, hw, sp, n_threads=4)
+    ok = r["status"] == 0
+    assert ok.any()
+    assert np.array_equal(r["pages_W"][ok], r["lines_W"][ok])
+    r2, _ = orc.estimate(k, with_hw(hw, l2_sections=3), sp, n_threads=4)
+    assert np.array_equal(r2["pages_W"][ok], r["lines_W"][ok])
+
+
+def test_pages_never_exceed_lines(orc):
+    sp = single_lattice_space((32, 4, 8), (256, 256, 256))
+    hw = with_hw(W.HW1, n_cu=108)
+    prev = None
+    for pb in (128, 256, 4096, 65536, 2 << 20):
+        r = one(orc, W.star_stencil(4), with_hw(hw, page_bytes=pb), sp)
+        assert 0 < r["pages_W"] <= r["lines_W"]
+        if prev is not None:
+            assert r["pages_W"] <= prev          # larger pages, fewer of them
+        prev = r["pages_W"]
+
+
+def test_multidim_rows_take_pages_of_their_own(orc):
+    # 64-wide rows of 8-byte values are 512 B: in the linear address space
+    # eight rows share a 4 KiB page, in the multi-dimensional one every row
+    # starts a page of its own
+    k = W.lattice_kernel_from([(0, 0, 0, 0, 0), (1, 1, 0, 0, 0)], n_fields=2)
+    sp = single_lattice_space((64, 4, 1), (64, 64, 64))
+    hw = with_hw(W.HW1, n_cu=16, page_bytes=4096)
+    lin = one(orc, k, hw, sp)
+    mdr = one(orc, md(k), hw, sp)
+    assert lin["lines_W"] == mdr["lines_W"]
+    assert lin["pages_W"] * 32 == lin["lines_W"]
+    assert mdr["pages_W"] * 4 == mdr["lines_W"]
+
+
+def test_pages_are_validated(orc):
+    sp = single_lattice_space((64, 2, 1), (64, 64, 64))
+    for bad in (-4096, 64, 3 * 4096, 2 << 30):
+        with pytest.raises(Exception):
+            orc.estimate(W.star_stencil(4), with_hw(W.HW1, page_bytes=bad), sp, n_threads=1)
