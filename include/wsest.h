@@ -168,6 +168,12 @@ typedef struct {
      * Sec. 6), and the occupancies O_W and O_L divide by l2_sections *
      * l2_bytes.  The block's own footprint (L1) is not affected. */
     int64_t l2_sections;
+    /* Translation page size in bytes, 0 = pages not counted; otherwise a
+     * power of two from line_bytes to 2^30.  The result's pages_W is then the
+     * number of distinct (field, page) pairs the wave's loads and stores
+     * touch, for the whole wave (not per L2 section): the program metric of
+     * a TLB model (Sec. 6, Conclusion and Outlook). */
+    int64_t page_bytes;
 } wse_hw;
 
 /* Register a hardware description; kept resident on the device. */
@@ -231,6 +237,8 @@ typedef struct {
      * layer sets and of the wave against its capacity, its load volume from
      * the L2 in sectors, its bytes per LUP and limiter */
     double O_L3[3], R_L3[3], O_W3, R_st3, v_l3_ld, bpl_l3, p_l3;
+    /* translation pages the wave touches (wse_hw.page_bytes; 0 when not counted) */
+    int64_t pages_W;
 } wse_result;
 
 #define WSE_PLAIN 0    /* one launch sequence per configuration, host sync between */
@@ -265,7 +273,7 @@ wse_status wse_estimate(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces,
  * until the process ends.  Rounds are launched directly, not replayed from
  * captured graphs.  The kernel and hardware tables must be registered
  * beforehand (registration allocates).
- * Limits: the request's records (about 1.3 KiB per configuration, plus its
+ * Limits: the request's records (about 1.4 KiB per configuration, plus its
  * spaces and folding expansions) must leave at least 16 MiB of the array
  * for tables, else WSE_ENOMEM and nothing runs; a configuration whose
  * tables exceed what is left gets status WSE_ENOMEM, as one exceeding the

@@ -543,6 +543,9 @@ wse_status wse_hw_register(wse_ctx* c, const wse_hw* h, int32_t* hw_id)
     if (h->l3_bytes < 0 || (h->l3_bytes > 0 && !(h->bw_l3 > 0)))
         return fail(WSE_EINVAL, "l3_bytes must be >= 0, with bw_l3 > 0 when there is a third level");
     if (h->l2_sections < 0 || h->l2_sections > 64) return fail(WSE_EINVAL, "l2_sections must be in [0, 64]");
+    if (h->page_bytes < 0 ||
+        (h->page_bytes > 0 && (!pow2(h->page_bytes) || h->page_bytes < h->line_bytes || h->page_bytes > (1 << 30))))
+        return fail(WSE_EINVAL, "page_bytes must be 0 or a power of two from line_bytes to 2^30");
     HwDev d;
     std::memset(&d, 0, sizeof(d));
     d.line_bytes = h->line_bytes;
@@ -571,6 +574,8 @@ wse_status wse_hw_register(wse_ctx* c, const wse_hw* h, int32_t* hw_id)
     d.l3_bytes = h->l3_bytes;
     d.bw_l3 = h->l3_bytes > 0 ? h->bw_l3 : 0.0;
     d.l2_sections = h->l2_sections > 1 ? h->l2_sections : 1;
+    d.page_bytes = h->page_bytes;
+    d.log2_page = h->page_bytes > 0 ? ilog2(h->page_bytes) : 0;
     for (int i = 0; i < 4; i++) {
         d.fit[i][0] = fits[i]->a;
         d.fit[i][1] = fits[i]->b;
@@ -1090,6 +1095,9 @@ static wse_status run_round(wse_ctx* c, RoundMem m, const std::vector<RoundItem>
         else if (g.smin >= 0) add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_B, PASS_L, g.l_units, per);
         for (int t = 0; t < N_TABLES; t++)
             if (table_used(g.tab[t])) add(LIST_COUNT, t, table_units(g.tab[t]), 1 << 16);
+        // page units over the wave's sector bitmaps (a hash configuration
+        // counts its pages while it counts the sector table)
+        if (g.page_mode == PAGES_BITMAP) add(LIST_COUNT, kCountPages, (int64_t)g.n_fields * g.pspan, 1 << 12);
     }
     RoundDesc rd;
     std::memset(&rd, 0, sizeof(rd));
@@ -1223,10 +1231,10 @@ extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t 
 }
 
 // Work list entries per configuration and round: at most four evaluation
-// passes and five counted tables.
-constexpr size_t kWorkPerConfig = 9;
+// passes, five counted tables and the page units.
+constexpr size_t kWorkPerConfig = 10;
 // Work list capacity of the no-allocation entry point (entries per round).
-constexpr size_t kScratchWork = 9 * 2048;
+constexpr size_t kScratchWork = kWorkPerConfig * 2048;
 // The table area of the no-allocation entry point is at least this large.
 constexpr size_t kScratchMinTables = (size_t)16 << 20;
 

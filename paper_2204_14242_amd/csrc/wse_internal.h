@@ -84,6 +84,8 @@ struct HwDev {
     int64_t l3_bytes;  // third cache level (0 = none)
     double bw_l3;
     int64_t l2_sections;  // L2 sections, >= 1; block k caches in section k mod l2_sections
+    int64_t page_bytes;   // translation page of the wave's page count (0 = not counted)
+    int32_t log2_page, pad;
 };
 
 struct Expansion {
@@ -135,8 +137,19 @@ struct Cfg {
     int64_t s_lo, s_hi;         // lattice kernels of one element size: smallest and largest
                                 // instruction byte offset (align + elem * c0); s_lo > s_hi if unknown
     TableDesc tab[N_TABLES];
+    // translation pages of the wave, counted from its sector set: 0 = off,
+    // PAGES_BITMAP = one count unit per (field, page) over the sector bitmaps,
+    // PAGES_HASH = the sector table's entries inserted into the page table ptab;
+    // page p of field f is key f * pspan + (p - pumin), rp = log2(page / sector)
+    int32_t page_mode, rp;
+    int32_t n_fields, pad4;
+    int64_t pumin, pspan;
+    TableDesc ptab;
     int64_t table_bytes;        // arena bytes this configuration needs
 };
+enum { PAGES_OFF = 0, PAGES_BITMAP = 1, PAGES_HASH = 2 };
+// counting work of the page units of a configuration (WorkEntry::what)
+constexpr int kCountPages = N_TABLES;
 
 // per-configuration accumulators (int64 atomics)
 struct Counters {
@@ -145,7 +158,8 @@ struct Counters {
     unsigned long long lines_L[3], shell[3];
     unsigned long long err;     // bit0 key out of range, bit1 table overflow
     unsigned long long lanes_L;
-    unsigned long long pad[2];
+    unsigned long long pages_W;
+    unsigned long long pad;
 };
 
 // a contiguous range of work of one configuration, split into equal items;
@@ -189,6 +203,7 @@ struct Result {  // identical layout to wse_result
     double O_l1, R_l1, v_l2l1_ld, O_W, R_st, O_L[3], R_L[3], v_dram_ld, v_dram_st;
     double bpl_l2, bpl_dram, p_l1, p_l2, p_dram, p_fp, perf;
     double O_L3[3], R_L3[3], O_W3, R_st3, v_l3_ld, bpl_l3, p_l3;
+    int64_t pages_W;
 };
 
 struct DevTables {

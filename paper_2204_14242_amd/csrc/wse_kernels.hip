@@ -515,13 +515,15 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
             const int64_t xlo = c.g + vmin[0], xhi = c.g + c.T[0] - 1 + vmax[0];
             const int64_t ylo = c.g + vmin[1], yhi = c.g + c.fold[1] * (c.T[1] - 1) + vmax[1];
             const int64_t zlo = c.g + vmin[2];
-            int64_t a = H.line_bytes, b = E1;   // q = lcm(line, elem) / elem elements
+            // (rows start on a page boundary where pages are counted)
+            const int64_t unit = H.page_bytes > H.line_bytes ? H.page_bytes : H.line_bytes;
+            int64_t a = unit, b = E1;   // q = lcm(unit, elem) / elem elements
             while (b) {
                 const int64_t t = a % b;
                 a = b;
                 b = t;
             }
-            const int64_t q = H.line_bytes / a;
+            const int64_t q = unit / a;
             const int64_t sx = xlo < 0 ? (-xlo + q - 1) / q * q : 0;
             c.wsy = (xhi + sx + 1 + q - 1) / q * q;
             c.wsz = c.wsy * (yhi - ylo + 1);
@@ -754,7 +756,43 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         bytes = (bytes + 255) & ~(int64_t)255;
     }
     c.dense = (dense_g[0] ? 1 : 0) | (dense_g[1] ? 2 : 0) | (w_lines_derived ? 4 : 0);
+    // translation pages of the wave, counted from its sector set: over the
+    // sector bitmaps per (field, page), or by inserting every entry of the
+    // sector hash table into a page table of its own
+    c.n_fields = K.n_fields;
+    c.page_mode = PAGES_OFF;
+    c.ptab.log2cap = 0;
+    c.ptab.words = 0;
+    c.ptab.tag_off = -1;
+    if (!bad && H.log2_page > 0 && table_used(c.tab[T_WSEC])) {
+        const TableDesc& TS = c.tab[T_WSEC];
+        c.rp = H.log2_page - H.log2_sector;
+        c.pumin = TS.umin >> c.rp;  // floor
+        c.pspan = ((TS.umin + TS.span - 1) >> c.rp) - c.pumin + 1;
+        if (dense_g[1]) {
+            c.page_mode = PAGES_BITMAP;
+        } else {
+            const uint64_t pkeys = (uint64_t)K.n_fields * (uint64_t)c.pspan;
+            const int64_t bound = pkeys < (uint64_t)c.evals[PASS_W] ? (int64_t)pkeys : c.evals[PASS_W];
+            int l2p = 0;
+            round_cap(bound, slack, &l2p);
+            if (l2p > 32) {
+                bad = 2;
+            } else {
+                c.ptab.umin = c.pumin;
+                c.ptab.span = c.pspan;
+                c.ptab.off = bytes;
+                c.ptab.log2cap = l2p;
+                c.ptab.pb = 0;
+                bytes += ((int64_t)1 << l2p) * 8;
+                bytes = (bytes + 255) & ~(int64_t)255;
+                c.page_mode = PAGES_HASH;
+            }
+        }
+    }
     if (bad) {
+        c.page_mode = PAGES_OFF;
+        c.ptab.log2cap = 0;
         c.status = bad == 2 ? -2 : -3;
         bytes = 0;
         c.dense = 0;
@@ -1941,6 +1979,46 @@ hipError_t launch_eval(const WorkEntry* work, const RoundDesc* rd, int which, De
 
 // ---------------------------------------------------------------- counting
 
+// Page units [i0, i1) of a configuration whose wave sets are bitmaps: unit u
+// is page pumin + u mod pspan of field u / pspan, counted when any sector of
+// it is set in the load or store bitmap of any L2 section.  One wave.
+__device__ void count_pages(const CfgR& c, const char* arena, const WorkEntry* W, int64_t item, int lane)
+{
+    const TableR& T = c.tab[T_WSEC];
+    const unsigned* bm = (const unsigned*)(arena + T.off);
+    const int64_t nw = T.words, span = T.span, umin = T.umin;
+    const int64_t nf = c.n_fields, nsec = c.nsec, pspan = c.pspan;
+    const int64_t psec = (int64_t)1 << c.rp;  // sectors per page
+    const int64_t local = item - W->item_start;
+    const int64_t i0 = local * W->per_item;
+    const int64_t i1 = i0 + W->per_item < W->n_units ? i0 + W->per_item : W->n_units;
+    int64_t n = 0;
+    for (int64_t u = i0 + lane; u < i1; u += kLanes) {
+        const int64_t f = u / pspan, p = c.pumin + u % pspan;
+        // the page's sectors inside the table's range, relative to umin
+        const int64_t s0 = p * psec, s1 = s0 + psec - 1;
+        const int64_t lo = (s0 > umin ? s0 : umin) - umin;
+        const int64_t hi = (s1 < umin + span - 1 ? s1 : umin + span - 1) - umin;
+        bool any = false;
+        for (int64_t sec = 0; sec < nsec && !any; sec++) {
+            const int64_t base = (f + nf * sec) * span;
+            const int64_t k0 = base + lo, k1 = base + hi;
+            for (int64_t w = k0 >> 5; w <= (k1 >> 5) && !any; w++) {
+                unsigned m = 0xffffffffu;
+                if (w == (k0 >> 5)) m &= 0xffffffffu << (k0 & 31);
+                if (w == (k1 >> 5)) m &= 0xffffffffu >> (31 - (k1 & 31));
+                any = ((bm[w] | bm[nw + w]) & m) != 0;
+            }
+        }
+        n += any;
+    }
+    n = wave_sum64(n);
+    if (lane == 0 && n) {
+        Counters* cc = (Counters*)readfirstlane_ptr(W->ctr);
+        atomicAdd(&cc->pages_W, (unsigned long long)n);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ work_all,
                                                const RoundDesc* __restrict__ rd)
 {
@@ -1955,6 +2033,10 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
     CfgR& c = *(CfgR*)readfirstlane_ptr(W->cfg);
     const char* arena = (const char*)readfirstlane_ptr(W->tables);
     int q = W->what;
+    if (q == kCountPages) {
+        count_pages(c, arena, W, item, lane);
+        continue;
+    }
     TableR& T = c.tab[q];
     const unsigned long long* slots = (const unsigned long long*)(arena + T.off);
     int64_t local = item - W->item_start;
@@ -2015,6 +2097,12 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
     }
     const unsigned* tags = q == T_WSEC && T.words == 0 ? (const unsigned*)(arena + T.tag_off) : nullptr;
     uint64_t pmask = ((uint64_t)1 << T.pb) - 1;
+    // the wave's pages from its sector hash table: each entry's page goes into
+    // the page table, and a page counts where its insert is the first
+    const bool page_hash = q == T_WSEC && T.words == 0 && c.page_mode == PAGES_HASH;
+    unsigned long long* pslots = page_hash ? (unsigned long long*)(arena + c.ptab.off) : nullptr;
+    int64_t n3 = 0;
+    bool overflow = false;
     for (int64_t i = i0 + lane; i < i1 && T.words == 0; i += kLanes) {
         unsigned long long e = slots[i];
         if (e == 0) continue;
@@ -2022,6 +2110,18 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
             bool ld = (e & 1) != 0;
             n0 += ld;
             n1 += (e & 2) != 0;
+            if (page_hash) {
+                // entry ((key + 1) << 2) | flags, key = us + (field + n_fields * section) * span
+                const uint64_t k0 = (e >> 2) - 1;
+                const uint64_t fsec = k0 / (uint64_t)T.span;
+                const int64_t us = (int64_t)(k0 - fsec * (uint64_t)T.span);
+                const int64_t f = (int64_t)(fsec % (uint64_t)c.n_fields);
+                const int64_t page = (T.umin + us) >> c.rp;
+                const uint64_t pk = (uint64_t)(f * c.pspan + (page - c.pumin));
+                const int ins = table_insert(pslots, c.ptab.log2cap, pk + 1, 0, MODE_SET);
+                n3 += ins > 0;
+                overflow |= ins < 0;
+            }
             if (ld && c.n_order > 0) {
                 unsigned tg = tags[i];
                 int64_t last = tg ? c.smin + (int64_t)tg - 1 : -1;
@@ -2042,6 +2142,8 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
     n0 = wave_sum64(n0);
     n1 = wave_sum64(n1);
     n2 = wave_sum64(n2);
+    n3 = wave_sum64(n3);
+    const bool any_overflow = __ballot(overflow) != 0;
     for (int d = 0; d < 3; d++) {
         sh[d] = wave_sum64(sh[d]);
         ll[d] = wave_sum64(ll[d]);
@@ -2054,6 +2156,8 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
         else if (q == T_WSEC) {
             atomicAdd(&cc->fpld_W, (unsigned long long)n0);
             atomicAdd(&cc->comp_st_W, (unsigned long long)n1);
+            if (n3) atomicAdd(&cc->pages_W, (unsigned long long)n3);
+            if (any_overflow) atomicOr(&cc->err, 2ull);
             if (lines_from_secs) atomicAdd(&cc->lines_W, (unsigned long long)n2);
             for (int d = 0; d < 3; d++)
                 if (sh[d]) atomicAdd(&cc->shell[d], (unsigned long long)sh[d]);
@@ -2150,6 +2254,7 @@ __global__ void k_reduce(const Cfg* cfgs, const Counters* ctr, int64_t n, DevTab
     r.comp_st_W = (int64_t)k.comp_st_W;
     r.up_st_W = (int64_t)k.up_st_W;
     r.lines_W = (int64_t)k.lines_W;
+    r.pages_W = c.page_mode != PAGES_OFF ? (int64_t)k.pages_W : 0;
     for (int d = 0; d < 3; d++) {
         r.s_layer[d] = c.s[d];
         r.lines_L[d] = c.s[d] >= 0 ? (int64_t)k.lines_L[d] : 0;

@@ -32,9 +32,9 @@ RESULT_DTYPE = np.dtype([
     ("bpl_l2", "<f8"), ("bpl_dram", "<f8"), ("p_l1", "<f8"), ("p_l2", "<f8"),
     ("p_dram", "<f8"), ("p_fp", "<f8"), ("perf", "<f8"),
     ("O_L3", "<f8", 3), ("R_L3", "<f8", 3), ("O_W3", "<f8"), ("R_st3", "<f8"), ("v_l3_ld", "<f8"),
-    ("bpl_l3", "<f8"), ("p_l3", "<f8"),
+    ("bpl_l3", "<f8"), ("p_l3", "<f8"), ("pages_W", "<i8"),
 ])
-assert RESULT_DTYPE.itemsize == 488
+assert RESULT_DTYPE.itemsize == 496
 
 
 class wse_field(C.Structure):
@@ -68,7 +68,7 @@ class wse_hw(C.Structure):
         ("l1_bytes", C.c_int64), ("l2_bytes", C.c_int64), ("clock_hz", C.c_double),
         ("bw_l2", C.c_double), ("bw_dram", C.c_double), ("flops_peak", C.c_double),
         ("fit_l1", wse_fit), ("fit_l2_y", wse_fit), ("fit_l2_z", wse_fit), ("fit_l2_store", wse_fit),
-        ("l3_bytes", C.c_int64), ("bw_l3", C.c_double), ("l2_sections", C.c_int64)]
+        ("l3_bytes", C.c_int64), ("bw_l3", C.c_double), ("l2_sections", C.c_int64), ("page_bytes", C.c_int64)]
 
 
 class wse_space(C.Structure):
@@ -181,6 +181,7 @@ def hw_struct(hw):
     h.l3_bytes = int(hw.get("l3_bytes", 0))
     h.bw_l3 = float(hw.get("bw_l3", 0.0))
     h.l2_sections = int(hw.get("l2_sections", 1))
+    h.page_bytes = int(hw.get("page_bytes", 0))
     return h
 
 

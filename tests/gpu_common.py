@@ -43,13 +43,13 @@ L3_FIELDS = ("O_L3", "R_L3", "O_W3", "R_st3", "v_l3_ld", "bpl_l3", "p_l3")
 
 def in_layout_of(got, want):
     """got's records in want's layout when want was stored before the third
-    cache level's fields existed: those fields must then hold what a
-    configuration without a third level reports (0, and p_l3 = +inf for a
-    configuration that ran)."""
+    cache level's fields and the page count existed: those fields must then
+    hold what a configuration without a third level and without a page size
+    reports (0, and p_l3 = +inf for a configuration that ran)."""
     if got.dtype == want.dtype:
         return got
     extra = [n for n in got.dtype.names if n not in want.dtype.names]
-    assert set(extra) <= set(L3_FIELDS), extra
+    assert set(extra) <= set(L3_FIELDS) | {"pages_W"}, extra
     ran = got["status"] == 0
     for n in extra:
         v = got[n]

@@ -281,3 +281,38 @@ def test_l2_sections(ctx, orc):
     specs.append((km, with_hw(W.HW1, n_cu=64, l2_sections=4), spm))
     got = check(ctx, orc, specs, "L2 sections")
     assert (got["status"] == 0).sum() >= len(got) - 4
+
+
+def test_page_counts(ctx, orc):
+    # translation pages of the wave: 4 KiB and 2 MiB pages on stencils of both
+    # element sizes, line-sized pages on the LBM kernel, random affine kernels,
+    # and pages with a sectioned L2 in the multi-dimensional address space
+    k = W.star_stencil(4)
+    sp = W.lattice_space([(64, 64, 64), (128, 128, 128)], min_threads=64, max_threads=1024,
+                         fy=(1, 2), fz=(1, 2), elems=[4, 8])
+    sp["explicit"] = sorted(random.Random(59).sample(range(2 * 2 * 4 * 230), 20))
+    kl = W.lbm_two_phase(8)
+    spl = W.lattice_space([(48, 32, 24)], min_threads=64, max_threads=256, exps=range(7))
+    spl["explicit"] = list(range(2, 97, 5))
+    specs = [(k, with_hw(W.HW1, page_bytes=4096), sp), (k, with_hw(W.HW1, page_bytes=2 << 20), sp),
+             (kl, with_hw(W.H2, page_bytes=128), spl)]
+    for seed in range(3):
+        rng = random.Random(800 + seed)
+        nf = rng.randint(1, 3)
+        fields = [(rng.choice([4, 8]), rng.choice([0, 40, -96])) for _ in range(nf)]
+        exprs = [(rng.randrange(nf), int(rng.random() < 0.3), rng.randint(-30, 30),
+                  *[rng.randint(-3, 3) * m for m in (1, 41, 1000)],
+                  *[rng.randint(-3, 3) * m for m in (1, 41, 1000)],
+                  *[rng.randint(-1, 1) * m for m in (1, 41, 1000)]) for _ in range(rng.randint(2, 7))]
+        hw = with_hw(TINY_HW, warp_size=8, n_cu=rng.randint(2, 5), page_bytes=rng.choice([128, 256, 1024]),
+                     l2_sections=rng.choice([1, 2]))
+        spa = W.affine_space([(rng.randint(2, 6), rng.randint(2, 4), rng.randint(1, 3))],
+                             min_threads=2, max_threads=64, exps=range(5))
+        specs.append((W.affine_kernel(fields, exprs), hw, spa))
+    km = dict(W.star_stencil(2, ghost=2), address_space="multidim")
+    spm = W.lattice_space([(60, 36, 20)], min_threads=32, max_threads=512, fy=(1, 2), elems=[8])
+    spm["explicit"] = list(range(3, 2 * 185, 13))
+    specs.append((km, with_hw(W.HW1, n_cu=64, l2_sections=4, page_bytes=4096), spm))
+    got = check(ctx, orc, specs, "page counts")
+    ran = got["status"] == 0
+    assert ran.sum() >= len(got) - 4 and (got["pages_W"][ran] > 0).all()
