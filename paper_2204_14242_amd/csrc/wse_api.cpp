@@ -928,7 +928,7 @@ struct RoundItem {
 // and instruction.
 static int64_t config_cost(const wse_ctx* c, const Cfg& g)
 {
-    const bool rows = c->row_ranges && g.kind == 0 && (g.dense & 2) != 0 && g.row_ok;
+    const bool rows = c->row_ranges && (g.dense & 2) != 0 && g.row_ok;
     if (!rows) return g.evals[PASS_B] + g.evals[PASS_W] + g.evals[PASS_L];
     return g.evals[PASS_B] + 4 * (g.w_rows + (g.smin >= 0 ? g.l_rows : 0)) * std::max(1, g.E);
 }
@@ -1075,14 +1075,16 @@ static wse_status run_round(wse_ctx* c, RoundMem m, const std::vector<RoundItem>
         // the wave's tables); hash tables: the layer pass probes the wave's
         // sector table, so it runs in the launch after the wave pass
         const bool lattice_bitmap = g.kind == 0 && (g.dense & 2) != 0;
-        // row ranges: lattice bitmap passes whose element fits a sector
-        const bool rows = c->row_ranges && lattice_bitmap && g.row_ok;
+        // row ranges: bitmap passes whose per-thread step along x fits a
+        // sector (lattice kernels in the leaner kernel, affine ones beside
+        // their block passes, the layer pass after the wave pass)
+        const bool rows = c->row_ranges && (g.dense & 2) != 0 && g.row_ok;
         const int64_t row_len = std::max<int64_t>(1, g.T[0]);
         int64_t per_rows = std::max<int64_t>(1, c->target_evals / (row_len * std::max(1, g.E)));
         per_rows = (per_rows + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
         add(LIST_EVAL_A, PASS_B, spb, per);
         if (rows) {
-            add(LIST_EVAL_DL, PASS_WR, g.w_rows, per_rows);
+            add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_WR, g.w_rows, per_rows);
             c->last_row_units += g.w_rows + (g.smin >= 0 ? g.l_rows : 0);
         }
         else add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_W, g.w_units, per);
@@ -1091,7 +1093,7 @@ static wse_status run_round(wse_ctx* c, RoundMem m, const std::vector<RoundItem>
         int64_t per_st = std::max<int64_t>(1, c->target_evals / ((int64_t)kLanes * n_st));
         per_st = (per_st + kWavesPerGroup - 1) / kWavesPerGroup * kWavesPerGroup;
         if (g.E > g.n_ld) add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_A, PASS_WS, (g.w1 - g.w0) * spb, per_st);
-        if (g.smin >= 0 && rows) add(LIST_EVAL_DL, PASS_LR, g.l_rows, per_rows);
+        if (g.smin >= 0 && rows) add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_B, PASS_LR, g.l_rows, per_rows);
         else if (g.smin >= 0) add(lattice_bitmap ? LIST_EVAL_DL : LIST_EVAL_B, PASS_L, g.l_units, per);
         for (int t = 0; t < N_TABLES; t++)
             if (table_used(g.tab[t])) add(LIST_COUNT, t, table_units(g.tab[t]), 1 << 16);

@@ -570,6 +570,14 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         for (int e = 0; e < c.E; e++) nld += ex[e].st == 0;
         c.n_ld = nld;
         c.uniform_elem = K.uniform_elem;
+        // row ranges: along a thread row inside one block every address moves
+        // by elem * (ct_x + cg_x) per thread, at most a sector (one L2 only)
+        bool rows = H.l2_sections <= 1;
+        for (int e = 0; e < c.E && rows; e++) {
+            const __int128 step = (__int128)K.elem[ex[e].f] * ((__int128)ex[e].ct[0] + ex[e].cg[0]);
+            rows = step >= -(__int128)H.sector_bytes && step <= (__int128)H.sector_bytes;
+        }
+        c.row_ok = rows;
     }
     for (int d = 0; d < 3; d++) c.nb[d] = (c.T[d] + c.b[d] - 1) / c.b[d];
     int64_t occ = H.max_threads_per_cu / c.P;
@@ -1477,6 +1485,99 @@ __device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, 
     }
 }
 
+// Wave or layer pass of an affine kernel whose addresses move by at most a
+// sector from thread to thread along x, on bitmaps, by row ranges.  The
+// units are the thread rows of the pass's blocks (row order); each lane takes
+// one instruction of the row, and in every block the row crosses the address
+// is affine in the thread's x with that step, so the sectors and lines of
+// the block's piece of the row are one key range from its end addresses.
+// The sets are the same as when every (thread, instruction) pair is evaluated.
+template <int PASS>
+__device__ __forceinline__ void run_rows_affine(PassCtx& P, Counters* ctr, int64_t j0, int64_t j1)
+{
+    CfgR& c = *P.c;
+    const int lane = lane_id();
+    const int ls = P.H->log2_sector, ll = P.H->log2_line;
+    const int64_t nb0 = c.nb[0], nb1 = c.nb[1];
+    const int64_t b0 = c.b[0], b1 = c.b[1];
+    const int lb1 = c.lb[1];
+    TableR& TS = c.tab[T_WSEC];
+    TableR& TL = c.tab[PASS == PASS_L ? T_LLINE : T_WLINE];
+    const bool do_sec = table_used(TS);
+    const int64_t umin_s = TS.umin, span_s = TS.span, umin_l = TL.umin, span_l = TL.span;
+    const uint32_t off_s = (uint32_t)((PASS == PASS_L ? TS.tag_off : TS.off) >> 2);
+    const uint32_t off_l = (uint32_t)(TL.off >> 2);
+    const uint32_t words_s = (uint32_t)TS.words, words_l = (uint32_t)TL.words;
+    const RowOrder ro = PASS == PASS_L ? row_order(c, c.smin, c.w0) : row_order(c, c.w0, c.w1);
+    const int64_t rows_per = (int64_t)c.b[1] * c.b[2];
+    const int n_order = c.n_order;
+    const int64_t s_band[2] = {n_order > 0 ? c.s[c.order[0]] : 0, n_order > 1 ? c.s[c.order[1]] : 0};
+    const bool rec_lines = PASS == PASS_L || !(c.dense & 4);
+    const int E = c.E;
+    int64_t acc_lanes = 0;
+    for (int e0 = 0; e0 < E; e0 += kLanes) {
+        const bool mine = e0 + lane < E;
+        IConst ic;
+        if (mine) ic = load_iconst<1, true>(P, e0 + lane, TS, TL);
+        else ic = IConst{0, 0, 0, 0, 1, {0, 0, 0}, {0, 0, 0}, 0};
+        for (int64_t u = j0 + P.wave; u < j1; u += kWavesPerGroup) {
+            const int64_t r = ro.r0 + u / rows_per;
+            const int64_t tr = u % rows_per;
+            const int64_t by = r % nb1, bz = r / nb1;
+            const int64_t ty = tr & (b1 - 1), tz = tr >> lb1;
+            const int64_t xa = r == ro.r0 ? ro.xa0 : 0;
+            const int64_t xe = r == ro.r0 ? ro.xb0 : (r == ro.rl ? ro.xbl : c.T[0]);
+            if (xa >= xe) continue;
+            if (e0 == 0) acc_lanes += xe - xa;
+            if (!mine) continue;
+            // the row's part of the address, without the block's x
+            const int64_t rowpart = ic.kt[1] * ty + ic.kt[2] * tz + ic.kb[1] * by + ic.kb[2] * bz;
+            for (int64_t bx = xa / b0; bx * b0 < xe; bx++) {
+                const int64_t x0 = bx * b0 > xa ? bx * b0 : xa;
+                const int64_t x1 = (bx + 1) * b0 < xe ? (bx + 1) * b0 : xe;
+                const int64_t k = bx + nb0 * r;
+                uint32_t band = 0;
+                if (PASS == PASS_L) {
+                    if (n_order > 1 && k < s_band[0]) band = 1;
+                    if (n_order > 2 && k < s_band[1]) band = 2;
+                }
+                const int64_t base = rowpart + ic.kb[0] * bx;
+                const int64_t a0 = ic.S + (int64_t)ic.elem * (base + ic.kt[0] * (x0 - bx * b0));
+                const int64_t a1 = ic.S + (int64_t)ic.elem * (base + ic.kt[0] * (x1 - 1 - bx * b0));
+                const int64_t a_lo = a0 < a1 ? a0 : a1, a_hi = a0 < a1 ? a1 : a0;
+                const int64_t ul_lo = (a_lo >> ll) - umin_l, ul_hi = (a_hi >> ll) - umin_l;
+                const int64_t us_lo = (a_lo >> ls) - umin_s, us_hi = (a_hi >> ls) - umin_s;
+                if (ul_lo < 0 || ul_hi >= span_l || (PASS == PASS_W && (us_lo < 0 || us_hi >= span_s))) {
+                    P.err |= 1;
+                    continue;
+                }
+                if (rec_lines)
+                    set_key_range(P, off_l + band * words_l, (uint32_t)(ul_lo + ic.fl - 1),
+                                  (uint32_t)(ul_hi + ic.fl - 1));
+                if (PASS == PASS_W) {
+                    set_key_range(P, off_s + (ic.st ? words_s : 0u), (uint32_t)(us_lo + ic.fs - 1),
+                                  (uint32_t)(us_hi + ic.fs - 1));
+                } else if (do_sec) {
+                    // layer sectors count only inside the wave's sector range
+                    const int64_t lo = us_lo < 0 ? 0 : us_lo, hi = us_hi >= span_s ? span_s - 1 : us_hi;
+                    if (lo <= hi)
+                        set_key_range(P, off_s + band * words_s, (uint32_t)(lo + ic.fs - 1),
+                                      (uint32_t)(hi + ic.fs - 1));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    flush_words(P);
+    __syncthreads();
+    const bool any_err = __ballot(P.err != 0) != 0;
+    if (lane == 0) {
+        if (PASS == PASS_W) atomicAdd(&ctr->lanes_W, (unsigned long long)acc_lanes);
+        else atomicAdd(&ctr->lanes_L, (unsigned long long)acc_lanes);
+        if (any_err) atomicOr(&ctr->err, 1ull);
+    }
+}
+
 // One pass (representative block, wave or layer interval) over the segments
 // [j0, j1) of 64 consecutive threads.  The workgroup's waves take
 // consecutive segments, one instruction per step.  Hash configurations
@@ -1949,6 +2050,8 @@ __global__ __launch_bounds__(256, LATTICE_BITMAP ? 7 : 1) void k_eval(const Work
             if (dense) {
                 if (pass == PASS_B) run_pass<PASS_B, 1, true>(P, cc, c.kB, j0, j1);
                 else if (pass == PASS_W) run_pass<PASS_W, 1, true>(P, cc, c.w0, j0, j1);
+                else if (pass == PASS_WR) run_rows_affine<PASS_W>(P, cc, j0, j1);
+                else if (pass == PASS_LR) run_rows_affine<PASS_L>(P, cc, j0, j1);
                 else run_pass<PASS_L, 1, true>(P, cc, c.smin, j0, j1);
             } else {
                 if (pass == PASS_B) run_pass<PASS_B, 1, false>(P, cc, c.kB, j0, j1);

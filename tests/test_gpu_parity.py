@@ -316,3 +316,34 @@ def test_page_counts(ctx, orc):
     got = check(ctx, orc, specs, "page counts")
     ran = got["status"] == 0
     assert ran.sum() >= len(got) - 4 and (got["pages_W"][ran] > 0).all()
+
+
+def affine_box_kernel(sy, sz, xstep=1, elem=8):
+    # a box-shaped affine kernel: a 7-point stencil over global coordinates
+    # (x moving by xstep elements per thread), plus a block-local read
+    loads = [(0, 0, 0, 0, 0, 0, 0, 0, 0, xstep, sy, sz)]
+    for c0 in (1, -1, sy, -sy, sz, -sz):
+        loads.append((0, 0, c0, 0, 0, 0, 0, 0, 0, xstep, sy, sz))
+    loads.append((0, 0, 5, -xstep, 3, 0, 2 * xstep, sy, 0, 0, 0, sz))
+    store = (1, 1, 0, 0, 0, 0, 0, 0, 0, xstep, sy, sz)
+    return W.affine_kernel([(elem, 0), (elem, 64)], loads + [store])
+
+
+def test_affine_row_ranges(ctx, orc):
+    # wave and layer sets of affine kernels from per-block row ranges: unit,
+    # doubled and reversed x steps, both element sizes; a step beyond a
+    # sector falls back to evaluating every thread
+    specs = []
+    for xstep, elem in ((1, 8), (2, 8), (-1, 4), (4, 8), (8, 8)):
+        k = affine_box_kernel(200, 200 * 70, xstep=xstep, elem=elem)
+        sp = W.affine_space([(4, 8, 6), (2, 16, 3)], min_threads=16, max_threads=256, exps=range(6))
+        hw = with_hw(W.HW1, n_cu=8, blocks_per_cu=2)
+        specs.append((k, hw, sp))
+    got = check(ctx, orc, specs, "affine row ranges")
+    assert (got["status"] == 0).all()
+    assert (got["s_layer"] >= 0).any()
+    st = ctx.last_stats()
+    if ctx.representation == "rows":
+        assert st["row_range_units"] > 0
+    else:
+        assert st["row_range_units"] == 0
