@@ -5,11 +5,14 @@ configurations, for hardware counters collected by rocprofv3 around it:
         python3 -m paper_2204_14242_amd.fit.measure PLAN.json MANIFEST.json
 
 PLAN.json: {"calibration_doubles": n, "configs": [{"domain": [nx, ny, nz],
-"shape": [bx, by, bz], "fold": [fy, fz]}, ...]}.  Every configuration runs
-twice (the second launch is the measured one); a plain copy of n doubles
-runs first, to scale the request counters to bytes.  MANIFEST.json lists the
-launches of the measurement kernels in order, so that the counter rows can
-be matched to them."""
+"shape": [bx, by, bz], "fold": [fy, fz], "kernel": "star25" | "lbm"}, ...]}.
+"star25" is the range-4 star stencil (star25 kernel, with folding); "lbm" the
+two-phase-LBM-shaped kernel of workloads.lbm_two_phase, run by the
+access-table kernel (gather, no folding) on one array per field.  Every
+configuration runs twice (the second launch is the measured one); a plain
+copy of n doubles runs first, to scale the request counters to bytes.
+MANIFEST.json lists the launches of the measurement kernels in order, so
+that the counter rows can be matched to them."""
 import ctypes as C
 import json
 import os
@@ -39,29 +42,87 @@ def main(plan_path, manifest_path):
     torch.cuda.synchronize()
     launches.append({"kernel": "copy1", "doubles": n})
     del a, b
+    lib.probe_lattice.restype = C.c_int32
+    lib.probe_lattice.argtypes = [C.c_void_p] * 4 + [C.c_int32] * 8 + [C.c_void_p]
     arrays = {}
     for i, cfg in enumerate(plan["configs"]):
         nx, ny, nz = cfg["domain"]
-        key = (nx, ny, nz)
+        kname = cfg.get("kernel", "star25")
+        key = (kname, nx, ny, nz)
         if key not in arrays:
             arrays.clear()
             torch.cuda.empty_cache()
-            size = (nx + 8) * (ny + 8) * (nz + 8)
-            src = torch.rand(size, dtype=torch.float64, device=dev)
-            dst = torch.zeros(size, dtype=torch.float64, device=dev)
-            arrays[key] = (src, dst)
-        src, dst = arrays[key]
+            arrays[key] = star_arrays(torch, dev, nx, ny, nz) if kname == "star25" else \
+                lattice_arrays(torch, dev, lbm_table(), nx, ny, nz)
         bx, by, bz = cfg["shape"]
         fy, fz = cfg["fold"]
         for rep in range(2):
-            if lib.probe_star25(src.data_ptr(), dst.data_ptr(), nx, ny, nz, bx, by, bz, fy, fz, st) != 0:
+            if kname == "star25":
+                src, dst = arrays[key]
+                rc = lib.probe_star25(src.data_ptr(), dst.data_ptr(), nx, ny, nz, bx, by, bz, fy, fz, st)
+            else:
+                if (fy, fz) != (1, 1):
+                    raise SystemExit(f"the access-table kernel runs without folding: {cfg}")
+                a = arrays[key]
+                rc = lib.probe_lattice(a["in"].data_ptr(), a["out"].data_ptr(), a["ld_field"].data_ptr(),
+                                       a["ld_off"].data_ptr(), a["n_ld"], a["n_st"], nx, ny, nz, bx, by, bz, st)
+            if rc != 0:
                 raise SystemExit(f"launch failed for {cfg}")
             torch.cuda.synchronize()
-            launches.append({"kernel": "star25", "config": i, "measured": rep == 1})
+            launches.append({"kernel": "star25" if kname == "star25" else "gather", "config": i,
+                             "measured": rep == 1})
         if i % 20 == 0:
             print(f"configuration {i} of {len(plan['configs'])} done", flush=True)
     json.dump({"launches": launches}, open(manifest_path, "w"))
     print("measurement done", flush=True)
+
+
+def star_arrays(torch, dev, nx, ny, nz):
+    size = (nx + 8) * (ny + 8) * (nz + 8)
+    return (torch.rand(size, dtype=torch.float64, device=dev), torch.zeros(size, dtype=torch.float64, device=dev))
+
+
+def lbm_table():
+    """The LBM kernel's accesses (field, is_store, dx, dy, dz) and field count."""
+    from paper_2204_14242_amd import workloads as W
+    k = W.lbm_two_phase(8)
+    return k["accesses"], len(k["fields"])
+
+
+def lattice_arrays(torch, dev, table, nx, ny, nz):
+    """One fp64 array per field, each holding the lattice (x fastest, no
+    ghost layers) between margins as wide as the largest offset, rounded to
+    16 elements so that every field's first point starts a 128-byte line
+    (the model's alignment 0), all in one allocation."""
+    accesses, n_fields = table
+    offs = [dx + nx * (dy + ny * dz) for (_, _, dx, dy, dz) in accesses]
+    margin = (max(abs(o) for o in offs) + 15) // 16 * 16
+    n = nx * ny * nz
+    stride = (n + 2 * margin + 15) // 16 * 16
+    store = torch.rand(n_fields * stride, dtype=torch.float64, device=dev)
+    base = store.data_ptr()
+    ptr = [base + 8 * (f * stride + margin) for f in range(n_fields)]
+    ld = [(f, o) for (f, st, *_), o in zip(accesses, offs) if not st]
+    st_fields = sorted({f for (f, st, *_) in accesses if st})
+    ld_fields = sorted({f for f, _ in ld})
+    slot = {f: i for i, f in enumerate(ld_fields)}
+    return {"store": store,
+            "in": torch.tensor([ptr[f] for f in ld_fields], dtype=torch.int64, device=dev),
+            "out": torch.tensor([ptr[f] for f in st_fields], dtype=torch.int64, device=dev),
+            "ld_field": torch.tensor([slot[f] for f, _ in ld], dtype=torch.int32, device=dev),
+            "ld_off": torch.tensor([o for _, o in ld], dtype=torch.int64, device=dev),
+            "n_ld": len(ld), "n_st": len(st_fields)}
+
+
+def lbm_plan(path):
+    """The LBM kernel on 64^3, 128^3 and 256^3 with 24 block shapes of
+    64..1024 threads each (no folding)."""
+    shapes = [(2 ** a, 2 ** b, 2 ** c) for a in range(11) for b in range(11) for c in range(11)
+              if 64 <= 2 ** (a + b + c) <= 1024]
+    pick = shapes[::len(shapes) // 24][:24]
+    cfgs = [{"domain": [d, d, d], "shape": list(s), "fold": [1, 1], "kernel": "lbm"}
+            for d in (64, 128, 256) for s in pick]
+    json.dump({"calibration_doubles": 1 << 28, "configs": cfgs}, open(path, "w"), indent=0)
 
 
 def default_plan(path):
@@ -83,5 +144,7 @@ def default_plan(path):
 if __name__ == "__main__":
     if sys.argv[1] == "plan":
         default_plan(sys.argv[2])
+    elif sys.argv[1] == "plan-lbm":
+        lbm_plan(sys.argv[2])
     else:
         main(sys.argv[1], sys.argv[2])

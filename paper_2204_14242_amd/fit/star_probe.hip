@@ -40,6 +40,34 @@ __global__ void star25(const double* __restrict__ src, double* __restrict__ dst,
         }
 }
 
+// A lattice kernel given by its access table: every thread of the
+// nx x ny x nz lattice (x fastest, no ghost layers: fields carry margins of
+// their own) sums its n_ld loads in[ld_field[a]][c + ld_off[a]] and writes
+// the sum to each of its n_st store fields at its own point.  The table is
+// uniform across the wave, so its entries come through scalar loads and the
+// vector memory traffic is the kernel's own.
+__global__ void gather(const double* const* __restrict__ in, double* const* __restrict__ out,
+                       const int32_t* __restrict__ ld_field, const int64_t* __restrict__ ld_off, int n_ld,
+                       int n_st, int nx, int ny, int nz)
+{
+    const int gx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gy = blockIdx.y * blockDim.y + threadIdx.y;
+    const int gz = blockIdx.z * blockDim.z + threadIdx.z;
+    if (gx >= nx || gy >= ny || gz >= nz) return;
+    const int64_t c = gx + (int64_t)nx * (gy + (int64_t)ny * gz);
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int a = 0;
+    for (; a + 4 <= n_ld; a += 4) {
+        v0 += in[ld_field[a]][c + ld_off[a]];
+        v1 += in[ld_field[a + 1]][c + ld_off[a + 1]];
+        v2 += in[ld_field[a + 2]][c + ld_off[a + 2]];
+        v3 += in[ld_field[a + 3]][c + ld_off[a + 3]];
+    }
+    for (; a < n_ld; a++) v0 += in[ld_field[a]][c + ld_off[a]];
+    const double v = (v0 + v1) + (v2 + v3);
+    for (int j = 0; j < n_st; j++) out[j][c] = v + j;
+}
+
 __global__ void copy1(const double* __restrict__ src, double* __restrict__ dst, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -76,6 +104,23 @@ int32_t probe_star25(const double* src, double* dst, int32_t nx, int32_t ny, int
     WSE_PROBE_CASE(8, 1) WSE_PROBE_CASE(8, 2) WSE_PROBE_CASE(8, 4) WSE_PROBE_CASE(8, 8)
 #undef WSE_PROBE_CASE
     return e == hipSuccess ? 0 : -4;
+}
+
+// The access-table lattice kernel (gather) over nx x ny x nz with blocks
+// bx x by x bz: in/out are device arrays of field pointers, ld_field/ld_off
+// device arrays of n_ld entries (field index into in, offset in elements).
+// Every field must hold the lattice plus a margin of the largest |offset| on
+// both sides.
+int32_t probe_lattice(const double* const* in, double* const* out, const int32_t* ld_field, const int64_t* ld_off,
+                      int32_t n_ld, int32_t n_st, int32_t nx, int32_t ny, int32_t nz, int32_t bx, int32_t by,
+                      int32_t bz, void* stream)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || bx < 1 || by < 1 || bz < 1 || (int64_t)bx * by * bz > 1024) return -1;
+    if (n_ld < 0 || n_st < 0 || !in || !out || !ld_field || !ld_off) return -1;
+    dim3 grid((nx + bx - 1) / bx, (ny + by - 1) / by, (nz + bz - 1) / bz);
+    hipLaunchKernelGGL(gather, grid, dim3(bx, by, bz), 0, (hipStream_t)stream, in, out, ld_field, ld_off, n_ld,
+                       n_st, nx, ny, nz);
+    return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
 // dst[i] = src[i] for i < n (one read and one write of 8 bytes each)
