@@ -142,7 +142,7 @@ struct Cfg {
     // PAGES_HASH = the sector table's entries inserted into the page table ptab;
     // page p of field f is key f * pspan + (p - pumin), rp = log2(page / sector)
     int32_t page_mode, rp;
-    int32_t n_fields, pad4;
+    int32_t n_fields, blk_order;  // blk_order: wave and layer passes in block order (general kernel)
     int64_t pumin, pspan;
     TableDesc ptab;
     int64_t table_bytes;        // arena bytes this configuration needs

@@ -764,6 +764,19 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         bytes = (bytes + 255) & ~(int64_t)255;
     }
     c.dense = (dense_g[0] ? 1 : 0) | (dense_g[1] ? 2 : 0) | (w_lines_derived ? 4 : 0);
+    // The general kernel walks a wave or layer pass in block order where
+    // that fills more of a segment's 64 lanes than row order (thread rows of
+    // T[0] threads against blocks of P threads); the lattice bitmap kernel
+    // keeps row order, which its run-end steps need.
+    c.blk_order = 0;
+    if (!(c.kind == 0 && dense_g[1])) {
+        const int64_t seg_row = (c.T[0] + kLanes - 1) / kLanes, seg_blk = c.segs_per_block;
+        if ((__int128)c.P * seg_row > (__int128)c.T[0] * seg_blk) {
+            c.blk_order = 1;
+            c.w_units = (c.w1 - c.w0) * seg_blk;
+            c.l_units = nL > 0 ? nL * seg_blk : 0;
+        }
+    }
     // translation pages of the wave, counted from its sector set: over the
     // sector bitmaps per (field, page), or by inserting every entry of the
     // sector hash table into a page table of its own
@@ -1584,7 +1597,7 @@ __device__ __forceinline__ void run_rows_affine(PassCtx& P, Counters* ctr, int64
 // insert into the workgroup's shared LDS sets (the waves move in lockstep so
 // that the keys they share meet there); bitmap configurations set their bits
 // in HBM directly and need no synchronisation.
-template <int PASS, int KIND, bool DENSE, bool RUNS = false>
+template <int PASS, int KIND, bool DENSE, bool RUNS = false, bool ROWORD = true>
 __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo, int64_t j0, int64_t j1)
 {
     CfgR& c = *P.c;
@@ -1608,7 +1621,10 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     int64_t acc_up_ld = 0, acc_up_st = 0, acc_cyc = 0, acc_lanes = 0, acc_warps = 0;
     // a lane whose key left its table's range (reported once, after the item)
     bool out_of_range = false;
-    constexpr bool ROW = PASS == PASS_W || PASS == PASS_L;  // row order
+    // wave and layer passes: row order, or block order (ROWORD false) where
+    // thread rows are short
+    constexpr bool WL = PASS == PASS_W || PASS == PASS_L;
+    constexpr bool ROW = WL && ROWORD;
     TableR& TS = c.tab[PASS == PASS_B ? T_BSEC : T_WSEC];
     TableR& TL = c.tab[PASS == PASS_L ? T_LLINE : (PASS == PASS_B ? T_BLINE : T_WLINE)];
     const int sec_pb = PASS == PASS_W ? 2 : (PASS == PASS_L ? tag_bits : 0);
@@ -1628,9 +1644,9 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     const bool w_lines = !(PASS == PASS_W && DENSE && (c.dense & 4));
     // an L2 of several sections: the wave and layer keys of block k lie in
     // key block k mod nsec (n_fields * span keys each)
-    const int nsec = ROW ? c.nsec : 1;
-    const int64_t sec_keys_s = ROW ? (int64_t)P.K->n_fields * span_s : 0;
-    const int64_t sec_keys_l = ROW ? (int64_t)P.K->n_fields * span_l : 0;
+    const int nsec = WL ? c.nsec : 1;
+    const int64_t sec_keys_s = WL ? (int64_t)P.K->n_fields * span_s : 0;
+    const int64_t sec_keys_l = WL ? (int64_t)P.K->n_fields * span_l : 0;
     // wave and layer passes: row order of their blocks; layer band
     // thresholds in recency order
     RowOrder ro;
@@ -1690,6 +1706,11 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 bcur[0] = bx;
                 bcur[1] = by;
                 bcur[2] = bz;
+                if (nsec > 1) {
+                    const int64_t sec = k % nsec;
+                    soff_s = sec * sec_keys_s;
+                    soff_l = sec * sec_keys_l;
+                }
             }
             const uint64_t vmask = __ballot(valid);
             const int64_t tcur[3] = {tx, ty, tz};
@@ -2036,26 +2057,37 @@ __global__ __launch_bounds__(256, LATTICE_BITMAP ? 7 : 1) void k_eval(const Work
             else run_pass<PASS_WS, 1, true>(P, cc, c.w0, j0, j1);
             continue;
         }
+        // wave and layer passes in block order where the configuration's thread
+        // rows are short (Cfg::blk_order)
+        const bool blk = __builtin_amdgcn_readfirstlane(c.blk_order) != 0;
         if (c.kind == 0) {
             if (dense) {
                 if (pass == PASS_B) run_pass<PASS_B, 0, true>(P, cc, c.kB, j0, j1);
+                else if (pass == PASS_W && blk) run_pass<PASS_W, 0, true, false, false>(P, cc, c.w0, j0, j1);
                 else if (pass == PASS_W) run_pass<PASS_W, 0, true>(P, cc, c.w0, j0, j1);
+                else if (blk) run_pass<PASS_L, 0, true, false, false>(P, cc, c.smin, j0, j1);
                 else run_pass<PASS_L, 0, true>(P, cc, c.smin, j0, j1);
             } else {
                 if (pass == PASS_B) run_pass<PASS_B, 0, false>(P, cc, c.kB, j0, j1);
+                else if (pass == PASS_W && blk) run_pass<PASS_W, 0, false, false, false>(P, cc, c.w0, j0, j1);
                 else if (pass == PASS_W) run_pass<PASS_W, 0, false>(P, cc, c.w0, j0, j1);
+                else if (blk) run_pass<PASS_L, 0, false, false, false>(P, cc, c.smin, j0, j1);
                 else run_pass<PASS_L, 0, false>(P, cc, c.smin, j0, j1);
             }
         } else {
             if (dense) {
                 if (pass == PASS_B) run_pass<PASS_B, 1, true>(P, cc, c.kB, j0, j1);
+                else if (pass == PASS_W && blk) run_pass<PASS_W, 1, true, false, false>(P, cc, c.w0, j0, j1);
                 else if (pass == PASS_W) run_pass<PASS_W, 1, true>(P, cc, c.w0, j0, j1);
                 else if (pass == PASS_WR) run_rows_affine<PASS_W>(P, cc, j0, j1);
                 else if (pass == PASS_LR) run_rows_affine<PASS_L>(P, cc, j0, j1);
+                else if (blk) run_pass<PASS_L, 1, true, false, false>(P, cc, c.smin, j0, j1);
                 else run_pass<PASS_L, 1, true>(P, cc, c.smin, j0, j1);
             } else {
                 if (pass == PASS_B) run_pass<PASS_B, 1, false>(P, cc, c.kB, j0, j1);
+                else if (pass == PASS_W && blk) run_pass<PASS_W, 1, false, false, false>(P, cc, c.w0, j0, j1);
                 else if (pass == PASS_W) run_pass<PASS_W, 1, false>(P, cc, c.w0, j0, j1);
+                else if (blk) run_pass<PASS_L, 1, false, false, false>(P, cc, c.smin, j0, j1);
                 else run_pass<PASS_L, 1, false>(P, cc, c.smin, j0, j1);
             }
         }
