@@ -767,13 +767,15 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
      * the sections (a unit two sections use is fetched by both). */
     const int64_t nsec = H->l2_sections > 1 ? H->l2_sections : 1;
     const int64_t nf = K->n_fields;
-    fset fpld, fpst, lw, pg;
+    fset fpld, fpst, lw, pg, fu;
     fset_init(&fpld, nf * nsec);
     fset_init(&fpst, nf * nsec);
     fset_init(&lw, nf * nsec);
     /* pages: one set per field for the whole wave (the translation of a page
      * is needed once however many blocks or sections use it) */
     fset_init(&pg, nf);
+    /* the wave's load sectors of all sections together */
+    fset_init(&fu, nf);
     int64_t lanes_W = 0;
     warpstats wsw;
     memset(&wsw, 0, sizeof(wsw));
@@ -787,6 +789,7 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
                 fset_add(c.ex[e].st ? &fpst : &fpld, c.ex[e].f + fo, wave_unit(&c, &c.ex[e], bid, tid, 0), 0);
                 fset_add(&lw, c.ex[e].f + fo, wave_unit(&c, &c.ex[e], bid, tid, 1), 0);
                 if (H->page_bytes > 0) fset_add(&pg, c.ex[e].f, wave_unit(&c, &c.ex[e], bid, tid, 2), 0);
+                if (nsec > 1 && !c.ex[e].st) fset_add(&fu, c.ex[e].f, wave_unit(&c, &c.ex[e], bid, tid, 0), 0);
             }
         }
     }
@@ -797,9 +800,11 @@ static void run_config(const orc_kernel* K, const orc_hw* H, const space_t* sp,
     r->lines_W = fset_size(&lw);
     r->up_st_W = wsw.up_st;
     r->pages_W = H->page_bytes > 0 ? fset_size(&pg) : 0;
+    r->dup_W = nsec > 1 ? r->fpld_W - fset_size(&fu) : 0;
     fset_free(&fpst);
     fset_free(&lw);
     fset_free(&pg);
+    fset_free(&fu);
 
     /* ---- layer-condition thread sets (Sec. 4.4.2) ----
      * C_d = { block(t - e_d) : t valid in the wave, t_d >= 1, block < w0 };

@@ -113,6 +113,10 @@ typedef struct {
     /* distinct (field, page) pairs of the wave's loads and stores (0 when
      * pages are not counted) */
     int64_t pages_W;
+    /* cache-line duplication of a sectioned L2 (Sec. 6): the wave's load
+     * sectors summed over the sections less those of their union; 0 with one
+     * L2 */
+    int64_t dup_W;
 } orc_result;
 
 int64_t orc_space_size(const orc_kernel* k, const orc_space* s);

@@ -943,3 +943,29 @@ def test_pages_are_validated(orc):
     for bad in (-4096, 64, 3 * 4096, 2 << 30):
         with pytest.raises(Exception):
             orc.estimate(W.star_stencil(4), with_hw(W.HW1, page_bytes=bad), sp, n_threads=1)
+
+
+def test_duplication_of_the_plane_wave(orc):
+    # the sectioned counts above against one L2: the eight sections load
+    # 166,144 sectors, their union is the one-L2 footprint of 9 * 16,384;
+    # with 64 sections the blocks' own footprints sum to 512 * 420
+    sp = single_lattice_space((64, 2, 1), (256, 256, 256), elem=8)
+    assert one(orc, W.star_stencil(4), W.HW1, sp)["dup_W"] == 0
+    r = one(orc, W.star_stencil(4), with_hw(W.HW1, l2_sections=8), sp)
+    assert r["dup_W"] == 166144 - 9 * 16384
+    r = one(orc, W.star_stencil(4), with_hw(W.HW1, l2_sections=64), sp)
+    assert r["dup_W"] == 512 * 420 - 9 * 16384
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_duplication_is_the_excess_over_one_l2(orc, seed):
+    # the union of the sections' load sectors is the one-L2 load footprint, so
+    # the duplication is the sectioned count less the one-L2 count
+    k, sp = random_affine(seed), tiny_space(seed)
+    one_l2, _ = orc.estimate(k, TINY_HW, sp, n_threads=4)
+    for s in (2, 3):
+        r, _ = orc.estimate(k, with_hw(TINY_HW, l2_sections=s), sp, n_threads=4)
+        ok = (r["status"] == 0) & (one_l2["status"] == 0)
+        assert ok.any()
+        assert np.array_equal(r["dup_W"][ok], r["fpld_W"][ok] - one_l2["fpld_W"][ok])
+        assert (r["dup_W"][ok] >= 0).all()
