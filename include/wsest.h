@@ -239,6 +239,10 @@ typedef struct {
     double O_L3[3], R_L3[3], O_W3, R_st3, v_l3_ld, bpl_l3, p_l3;
     /* translation pages the wave touches (wse_hw.page_bytes; 0 when not counted) */
     int64_t pages_W;
+    /* cache-line duplication across L2 sections (wse_hw.l2_sections > 1,
+     * Sec. 6): the wave's load sectors summed over the sections less their
+     * union, in sectors; 0 with one L2 */
+    int64_t dup_W;
 } wse_result;
 
 #define WSE_PLAIN 0    /* one launch sequence per configuration, host sync between */

@@ -1100,6 +1100,9 @@ static wse_status run_round(wse_ctx* c, RoundMem m, const std::vector<RoundItem>
         // page units over the wave's sector bitmaps (a hash configuration
         // counts its pages while it counts the sector table)
         if (g.page_mode == PAGES_BITMAP) add(LIST_COUNT, kCountPages, (int64_t)g.n_fields * g.pspan, 1 << 12);
+        // the sections' union over the load bitmap, 32 keys per unit
+        if (g.nsec > 1 && (g.dense & 2) && table_used(g.tab[T_WSEC]))
+            add(LIST_COUNT, kCountUnion, ((int64_t)g.n_fields * g.tab[T_WSEC].span + 31) / 32, 1 << 14);
     }
     RoundDesc rd;
     std::memset(&rd, 0, sizeof(rd));
@@ -1233,8 +1236,8 @@ extern "C" wse_status wse_estimate(wse_ctx* c, const wse_space* spaces, int32_t 
 }
 
 // Work list entries per configuration and round: at most four evaluation
-// passes, five counted tables and the page units.
-constexpr size_t kWorkPerConfig = 10;
+// passes, five counted tables, the page units and the sections' union.
+constexpr size_t kWorkPerConfig = 11;
 // Work list capacity of the no-allocation entry point (entries per round).
 constexpr size_t kScratchWork = kWorkPerConfig * 2048;
 // The table area of the no-allocation entry point is at least this large.

@@ -145,11 +145,16 @@ struct Cfg {
     int32_t n_fields, blk_order;  // blk_order: wave and layer passes in block order (general kernel)
     int64_t pumin, pspan;
     TableDesc ptab;
+    // the wave's load sectors of all L2 sections together (nsec > 1): over
+    // the load bitmap's section blocks, or a table of section-free keys
+    TableDesc utab;
     int64_t table_bytes;        // arena bytes this configuration needs
 };
 enum { PAGES_OFF = 0, PAGES_BITMAP = 1, PAGES_HASH = 2 };
 // counting work of the page units of a configuration (WorkEntry::what)
 constexpr int kCountPages = N_TABLES;
+// counting work of the union of the L2 sections' load sectors (bitmaps)
+constexpr int kCountUnion = N_TABLES + 1;
 
 // per-configuration accumulators (int64 atomics)
 struct Counters {
@@ -159,7 +164,7 @@ struct Counters {
     unsigned long long err;     // bit0 key out of range, bit1 table overflow
     unsigned long long lanes_L;
     unsigned long long pages_W;
-    unsigned long long pad;
+    unsigned long long fpld_U;  // wave load sectors of all L2 sections together
 };
 
 // a contiguous range of work of one configuration, split into equal items;
@@ -204,6 +209,7 @@ struct Result {  // identical layout to wse_result
     double bpl_l2, bpl_dram, p_l1, p_l2, p_dram, p_fp, perf;
     double O_L3[3], R_L3[3], O_W3, R_st3, v_l3_ld, bpl_l3, p_l3;
     int64_t pages_W;
+    int64_t dup_W;
 };
 
 struct DevTables {

@@ -811,9 +811,32 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
             }
         }
     }
+    // hash configurations of a sectioned L2: a table of the wave's section-free
+    // load sector keys, filled while the sector table is counted
+    c.utab.log2cap = 0;
+    c.utab.words = 0;
+    c.utab.tag_off = -1;
+    if (!bad && c.nsec > 1 && table_used(c.tab[T_WSEC]) && !dense_g[1]) {
+        const uint64_t ukeys = (uint64_t)K.n_fields * (uint64_t)c.tab[T_WSEC].span;
+        const int64_t bound = ukeys < (uint64_t)c.evals[PASS_W] ? (int64_t)ukeys : c.evals[PASS_W];
+        int l2u = 0;
+        round_cap(bound, slack, &l2u);
+        if (l2u > 32) {
+            bad = 2;
+        } else {
+            c.utab.umin = c.tab[T_WSEC].umin;
+            c.utab.span = c.tab[T_WSEC].span;
+            c.utab.off = bytes;
+            c.utab.log2cap = l2u;
+            c.utab.pb = 0;
+            bytes += ((int64_t)1 << l2u) * 8;
+            bytes = (bytes + 255) & ~(int64_t)255;
+        }
+    }
     if (bad) {
         c.page_mode = PAGES_OFF;
         c.ptab.log2cap = 0;
+        c.utab.log2cap = 0;
         c.status = bad == 2 ? -2 : -3;
         bytes = 0;
         c.dense = 0;
@@ -2114,6 +2137,43 @@ hipError_t launch_eval(const WorkEntry* work, const RoundDesc* rd, int which, De
 
 // ---------------------------------------------------------------- counting
 
+// Units [i0, i1) of the union of the L2 sections' wave load sectors, on
+// bitmaps: unit u is the section-free keys [32u, 32u + 32) (of n_fields *
+// span), read at that offset in every section's key block of the load bitmap
+// (a block need not start on a word: two words and a shift; the last
+// section's read may reach the store bitmap's first word, which the mask of
+// the last unit, or the next section's keys, leave out).  One wave.
+__device__ void count_union(const CfgR& c, const char* arena, const WorkEntry* W, int64_t item, int lane)
+{
+    const TableR& T = c.tab[T_WSEC];
+    const unsigned* bm = (const unsigned*)(arena + T.off);
+    const int64_t B = (int64_t)c.n_fields * T.span, nsec = c.nsec;
+    const int64_t local = item - W->item_start;
+    const int64_t i0 = local * W->per_item;
+    const int64_t i1 = i0 + W->per_item < W->n_units ? i0 + W->per_item : W->n_units;
+    int64_t n = 0;
+    for (int64_t u = i0 + lane; u < i1; u += kLanes) {
+        const int64_t k0 = 32 * u;
+        unsigned acc = 0;
+        for (int64_t sec = 0; sec < nsec; sec++) {
+            const int64_t off = sec * B + k0;
+            const int64_t w = off >> 5;
+            const int sh = (int)(off & 31);
+            unsigned x = bm[w] >> sh;
+            if (sh) x |= bm[w + 1] << (32 - sh);
+            acc |= x;
+        }
+        const int64_t left = B - k0;
+        if (left < 32) acc &= (1u << left) - 1u;
+        n += __popc(acc);
+    }
+    n = wave_sum64(n);
+    if (lane == 0 && n) {
+        Counters* cc = (Counters*)readfirstlane_ptr(W->ctr);
+        atomicAdd(&cc->fpld_U, (unsigned long long)n);
+    }
+}
+
 // Page units [i0, i1) of a configuration whose wave sets are bitmaps: unit u
 // is page pumin + u mod pspan of field u / pspan, counted when any sector of
 // it is set in the load or store bitmap of any L2 section.  One wave.
@@ -2170,6 +2230,10 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
     int q = W->what;
     if (q == kCountPages) {
         count_pages(c, arena, W, item, lane);
+        continue;
+    }
+    if (q == kCountUnion) {
+        count_union(c, arena, W, item, lane);
         continue;
     }
     TableR& T = c.tab[q];
@@ -2236,7 +2300,10 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
     // the page table, and a page counts where its insert is the first
     const bool page_hash = q == T_WSEC && T.words == 0 && c.page_mode == PAGES_HASH;
     unsigned long long* pslots = page_hash ? (unsigned long long*)(arena + c.ptab.off) : nullptr;
-    int64_t n3 = 0;
+    // the sections' union of load sectors likewise, by section-free keys
+    const bool union_hash = q == T_WSEC && T.words == 0 && c.utab.log2cap > 0;
+    unsigned long long* uslots = union_hash ? (unsigned long long*)(arena + c.utab.off) : nullptr;
+    int64_t n3 = 0, n4 = 0;
     bool overflow = false;
     for (int64_t i = i0 + lane; i < i1 && T.words == 0; i += kLanes) {
         unsigned long long e = slots[i];
@@ -2245,8 +2312,19 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
             bool ld = (e & 1) != 0;
             n0 += ld;
             n1 += (e & 2) != 0;
-            if (page_hash) {
+            if (page_hash || (union_hash && ld)) {
                 // entry ((key + 1) << 2) | flags, key = us + (field + n_fields * section) * span
+                const uint64_t k0 = (e >> 2) - 1;
+                const uint64_t fsec = k0 / (uint64_t)T.span;
+                const int64_t us = (int64_t)(k0 - fsec * (uint64_t)T.span);
+                const int64_t f = (int64_t)(fsec % (uint64_t)c.n_fields);
+                if (union_hash && ld) {
+                    const int ins = table_insert(uslots, c.utab.log2cap, (uint64_t)(f * T.span + us) + 1, 0, MODE_SET);
+                    n4 += ins > 0;
+                    overflow |= ins < 0;
+                }
+            }
+            if (page_hash) {
                 const uint64_t k0 = (e >> 2) - 1;
                 const uint64_t fsec = k0 / (uint64_t)T.span;
                 const int64_t us = (int64_t)(k0 - fsec * (uint64_t)T.span);
@@ -2278,6 +2356,7 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
     n1 = wave_sum64(n1);
     n2 = wave_sum64(n2);
     n3 = wave_sum64(n3);
+    n4 = wave_sum64(n4);
     const bool any_overflow = __ballot(overflow) != 0;
     for (int d = 0; d < 3; d++) {
         sh[d] = wave_sum64(sh[d]);
@@ -2292,6 +2371,7 @@ __global__ __launch_bounds__(256) void k_count(const WorkEntry* __restrict__ wor
             atomicAdd(&cc->fpld_W, (unsigned long long)n0);
             atomicAdd(&cc->comp_st_W, (unsigned long long)n1);
             if (n3) atomicAdd(&cc->pages_W, (unsigned long long)n3);
+            if (n4) atomicAdd(&cc->fpld_U, (unsigned long long)n4);
             if (any_overflow) atomicOr(&cc->err, 2ull);
             if (lines_from_secs) atomicAdd(&cc->lines_W, (unsigned long long)n2);
             for (int d = 0; d < 3; d++)
@@ -2386,6 +2466,7 @@ __global__ void k_reduce(const Cfg* cfgs, const Counters* ctr, int64_t n, DevTab
     r.blocks_W = c.w1 - c.w0;
     r.lups_W = (int64_t)k.lanes_W * lpt;
     r.fpld_W = (int64_t)k.fpld_W;
+    r.dup_W = c.nsec > 1 ? r.fpld_W - (int64_t)k.fpld_U : 0;
     r.comp_st_W = (int64_t)k.comp_st_W;
     r.up_st_W = (int64_t)k.up_st_W;
     r.lines_W = (int64_t)k.lines_W;

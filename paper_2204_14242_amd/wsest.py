@@ -32,9 +32,9 @@ RESULT_DTYPE = np.dtype([
     ("bpl_l2", "<f8"), ("bpl_dram", "<f8"), ("p_l1", "<f8"), ("p_l2", "<f8"),
     ("p_dram", "<f8"), ("p_fp", "<f8"), ("perf", "<f8"),
     ("O_L3", "<f8", 3), ("R_L3", "<f8", 3), ("O_W3", "<f8"), ("R_st3", "<f8"), ("v_l3_ld", "<f8"),
-    ("bpl_l3", "<f8"), ("p_l3", "<f8"), ("pages_W", "<i8"),
+    ("bpl_l3", "<f8"), ("p_l3", "<f8"), ("pages_W", "<i8"), ("dup_W", "<i8"),
 ])
-assert RESULT_DTYPE.itemsize == 496
+assert RESULT_DTYPE.itemsize == 504
 
 
 class wse_field(C.Structure):

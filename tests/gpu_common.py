@@ -49,7 +49,7 @@ def in_layout_of(got, want):
     if got.dtype == want.dtype:
         return got
     extra = [n for n in got.dtype.names if n not in want.dtype.names]
-    assert set(extra) <= set(L3_FIELDS) | {"pages_W"}, extra
+    assert set(extra) <= set(L3_FIELDS) | {"pages_W", "dup_W"}, extra
     ran = got["status"] == 0
     for n in extra:
         v = got[n]

@@ -281,6 +281,8 @@ def test_l2_sections(ctx, orc):
     specs.append((km, with_hw(W.HW1, n_cu=64, l2_sections=4), spm))
     got = check(ctx, orc, specs, "L2 sections")
     assert (got["status"] == 0).sum() >= len(got) - 4
+    # every family duplicates lines across its sections
+    assert (got["dup_W"][got["status"] == 0] > 0).mean() > 0.5
 
 
 def test_page_counts(ctx, orc):
