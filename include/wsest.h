@@ -312,13 +312,13 @@ typedef struct {
                                    group has a key range of at most 2^bitmap_log2 times the
                                    evaluations that reach it (and below 2^32 keys); 0 = always
                                    hash tables (0 .. 8) */
-    int32_t row_ranges;         /* 1: configurations on bitmaps with one L2 fill the wave and
-                                   layer sets from the address range each instruction covers
-                                   along a thread row, instead of evaluating every (thread,
-                                   instruction) pair: lattice kernels whose element fits a sector
-                                   (whole rows), affine kernels whose address moves by at most a
-                                   sector per thread along x (each block's piece of a row); same
-                                   results; 0 = evaluate (0, 1) */
+    int32_t row_ranges;         /* 1: configurations on bitmaps fill the wave and layer sets
+                                   from the address range each instruction covers along a thread
+                                   row, instead of evaluating every (thread, instruction) pair:
+                                   lattice kernels whose element fits a sector (whole rows, or each
+                                   block's piece of a row with a sectioned L2), affine kernels whose
+                                   address moves by at most a sector per thread along x (each
+                                   block's piece of a row); same results; 0 = evaluate (0, 1) */
     int32_t pad;                /* 0 */
 } wse_tuning;
 

@@ -484,8 +484,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         c.E = X.E;
         c.n_ld = X.n_ld;
         c.uniform_elem = c.elem ? c.elem : K.uniform_elem;
-        // (row ranges span blocks of several L2 sections: one L2 only)
-        c.row_ok = c.uniform_elem > 0 && c.uniform_elem <= H.sector_bytes && H.l2_sections <= 1;
+        c.row_ok = c.uniform_elem > 0 && c.uniform_elem <= H.sector_bytes;
         c.wsy = c.sy;
         c.wsz = c.sz;
         c.wabase = 0;
@@ -571,8 +570,8 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         c.n_ld = nld;
         c.uniform_elem = K.uniform_elem;
         // row ranges: along a thread row inside one block every address moves
-        // by elem * (ct_x + cg_x) per thread, at most a sector (one L2 only)
-        bool rows = H.l2_sections <= 1;
+        // by elem * (ct_x + cg_x) per thread, at most a sector
+        bool rows = true;
         for (int e = 0; e < c.E && rows; e++) {
             const __int128 step = (__int128)K.elem[ex[e].f] * ((__int128)ex[e].ct[0] + ex[e].cg[0]);
             rows = step >= -(__int128)H.sector_bytes && step <= (__int128)H.sector_bytes;
@@ -1449,6 +1448,9 @@ __device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, 
     const RowOrder ro = PASS == PASS_L ? row_order(c, c.smin, c.w0) : row_order(c, c.w0, c.w1);
     const int64_t rows_per = b1 * b2;
     const int n_order = c.n_order;
+    // an L2 of several sections: key block k mod nsec for block k
+    const int nsec = c.nsec;
+    const int64_t sec_keys_s = (int64_t)P.K->n_fields * span_s, sec_keys_l = (int64_t)P.K->n_fields * span_l;
     const int64_t s_band[2] = {n_order > 0 ? c.s[c.order[0]] : 0, n_order > 1 ? c.s[c.order[1]] : 0};
     const int E = c.E;
     int64_t acc_lanes = 0;
@@ -1479,7 +1481,40 @@ __device__ __forceinline__ void run_rows(PassCtx& P, Counters* ctr, int64_t j0, 
                 if (n_order < 2) cut[1] = xa;
             }
             const int64_t rowbase = g + sy * (f1 * gy + g) + sz * (f2 * gz + g);
-            if (mine) {
+            if (mine && nsec > 1) {
+                // a sectioned L2: one range per block piece of the row, keyed in
+                // its block's section
+                for (int64_t bx = xa / b0; bx * b0 < xe; bx++) {
+                    const int64_t x0 = bx * b0 > xa ? bx * b0 : xa;
+                    const int64_t x1 = (bx + 1) * b0 < xe ? (bx + 1) * b0 : xe;
+                    const int64_t k = bx + nb0 * r;
+                    uint32_t band = 0;
+                    if (PASS == PASS_L && n_order > 1 && k < s_band[0])
+                        band = (n_order > 2 && k < s_band[1]) ? 2u : 1u;
+                    const int64_t sec = k % nsec;
+                    const int64_t so_s = sec * sec_keys_s, so_l = sec * sec_keys_l;
+                    const int64_t a_lo = (rowbase + x0) * uelem + ic.S;
+                    const int64_t a_hi = (rowbase + x1 - 1) * uelem + ic.S;
+                    const int64_t ul_lo = (a_lo >> ll) - umin_l, ul_hi = (a_hi >> ll) - umin_l;
+                    const int64_t us_lo = (a_lo >> ls) - umin_s, us_hi = (a_hi >> ls) - umin_s;
+                    if (ul_lo < 0 || ul_hi >= span_l || (PASS == PASS_W && (us_lo < 0 || us_hi >= span_s))) {
+                        P.err |= 1;
+                        continue;
+                    }
+                    if (PASS == PASS_L || !(c.dense & 4))
+                        set_key_range(P, off_l + band * words_l, (uint32_t)(ul_lo + ic.fl - 1 + so_l),
+                                      (uint32_t)(ul_hi + ic.fl - 1 + so_l));
+                    if (PASS == PASS_W) {
+                        set_key_range(P, off_s + (ic.st ? words_s : 0u), (uint32_t)(us_lo + ic.fs - 1 + so_s),
+                                      (uint32_t)(us_hi + ic.fs - 1 + so_s));
+                    } else if (do_sec) {
+                        const int64_t lo = us_lo < 0 ? 0 : us_lo, hi = us_hi >= span_s ? span_s - 1 : us_hi;
+                        if (lo <= hi)
+                            set_key_range(P, off_s + band * words_s, (uint32_t)(lo + ic.fs - 1 + so_s),
+                                          (uint32_t)(hi + ic.fs - 1 + so_s));
+                    }
+                }
+            } else if (mine) {
                 for (int band = 0; band < (PASS == PASS_L ? n_order : 1); band++) {
                     // band 0: [cut[2], xe); band 1: [cut[1], cut[2]); band 2: [xa, cut[1])
                     const int64_t x0 = PASS == PASS_L ? (band == 0 ? cut[2] : (band == 1 ? cut[1] : xa)) : xa;
@@ -1549,6 +1584,8 @@ __device__ __forceinline__ void run_rows_affine(PassCtx& P, Counters* ctr, int64
     const int n_order = c.n_order;
     const int64_t s_band[2] = {n_order > 0 ? c.s[c.order[0]] : 0, n_order > 1 ? c.s[c.order[1]] : 0};
     const bool rec_lines = PASS == PASS_L || !(c.dense & 4);
+    const int nsec = c.nsec;
+    const int64_t sec_keys_s = (int64_t)P.K->n_fields * span_s, sec_keys_l = (int64_t)P.K->n_fields * span_l;
     const int E = c.E;
     int64_t acc_lanes = 0;
     for (int e0 = 0; e0 < E; e0 += kLanes) {
@@ -1578,6 +1615,9 @@ __device__ __forceinline__ void run_rows_affine(PassCtx& P, Counters* ctr, int64
                     if (n_order > 2 && k < s_band[1]) band = 2;
                 }
                 const int64_t base = rowpart + ic.kb[0] * bx;
+                // the block's L2 section (key block k mod nsec)
+                const int64_t so_s = nsec > 1 ? (k % nsec) * sec_keys_s : 0;
+                const int64_t so_l = nsec > 1 ? (k % nsec) * sec_keys_l : 0;
                 const int64_t a0 = ic.S + (int64_t)ic.elem * (base + ic.kt[0] * (x0 - bx * b0));
                 const int64_t a1 = ic.S + (int64_t)ic.elem * (base + ic.kt[0] * (x1 - 1 - bx * b0));
                 const int64_t a_lo = a0 < a1 ? a0 : a1, a_hi = a0 < a1 ? a1 : a0;
@@ -1588,17 +1628,17 @@ __device__ __forceinline__ void run_rows_affine(PassCtx& P, Counters* ctr, int64
                     continue;
                 }
                 if (rec_lines)
-                    set_key_range(P, off_l + band * words_l, (uint32_t)(ul_lo + ic.fl - 1),
-                                  (uint32_t)(ul_hi + ic.fl - 1));
+                    set_key_range(P, off_l + band * words_l, (uint32_t)(ul_lo + ic.fl - 1 + so_l),
+                                  (uint32_t)(ul_hi + ic.fl - 1 + so_l));
                 if (PASS == PASS_W) {
-                    set_key_range(P, off_s + (ic.st ? words_s : 0u), (uint32_t)(us_lo + ic.fs - 1),
-                                  (uint32_t)(us_hi + ic.fs - 1));
+                    set_key_range(P, off_s + (ic.st ? words_s : 0u), (uint32_t)(us_lo + ic.fs - 1 + so_s),
+                                  (uint32_t)(us_hi + ic.fs - 1 + so_s));
                 } else if (do_sec) {
                     // layer sectors count only inside the wave's sector range
                     const int64_t lo = us_lo < 0 ? 0 : us_lo, hi = us_hi >= span_s ? span_s - 1 : us_hi;
                     if (lo <= hi)
-                        set_key_range(P, off_s + band * words_s, (uint32_t)(lo + ic.fs - 1),
-                                      (uint32_t)(hi + ic.fs - 1));
+                        set_key_range(P, off_s + band * words_s, (uint32_t)(lo + ic.fs - 1 + so_s),
+                                      (uint32_t)(hi + ic.fs - 1 + so_s));
                 }
             }
         }

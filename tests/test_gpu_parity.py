@@ -283,6 +283,8 @@ def test_l2_sections(ctx, orc):
     assert (got["status"] == 0).sum() >= len(got) - 4
     # every family duplicates lines across its sections
     assert (got["dup_W"][got["status"] == 0] > 0).mean() > 0.5
+    # row ranges run with sections too (per block piece of a row)
+    assert (ctx.last_stats()["row_range_units"] > 0) == (ctx.representation == "rows")
 
 
 def test_page_counts(ctx, orc):
