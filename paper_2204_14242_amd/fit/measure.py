@@ -125,6 +125,18 @@ def lbm_plan(path):
     json.dump({"calibration_doubles": 1 << 28, "configs": cfgs}, open(path, "w"), indent=0)
 
 
+def combined_plan(path):
+    """The star stencil's default plan followed by the LBM plan, in one
+    measurement run."""
+    default_plan(path)
+    plan = json.load(open(path))
+    for c in plan["configs"]:
+        c["kernel"] = "star25"
+    lbm_plan(path)
+    plan["configs"] += json.load(open(path))["configs"]
+    json.dump(plan, open(path, "w"), indent=0)
+
+
 def default_plan(path):
     """The measured configurations: 48 block shapes of 64..1024 threads on
     256^3 (L1 and short layer sets), and the constant-volume domain-size scan
@@ -146,5 +158,7 @@ if __name__ == "__main__":
         default_plan(sys.argv[2])
     elif sys.argv[1] == "plan-lbm":
         lbm_plan(sys.argv[2])
+    elif sys.argv[1] == "plan-all":
+        combined_plan(sys.argv[2])
     else:
         main(sys.argv[1], sys.argv[2])
