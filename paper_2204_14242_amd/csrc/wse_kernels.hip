@@ -1837,7 +1837,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             constexpr int MODE = decltype(mode_tag)::value;
             constexpr bool FAST = MODE >= 1;
             constexpr bool CHECK = MODE == 0;
-            for (int q = 0; q < n_in; q++) {
+            _Pragma("unroll 2") for (int q = 0; q < n_in; q++) {
                 int new0 = 0, new1 = 0;
                 if (vmask) {
                     const int64_t S = readlane64(ic.S, q);
