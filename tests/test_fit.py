@@ -34,3 +34,39 @@ def test_dram_model_limits():
     lose = [0, 0, 0] * 3          # R = 0: fresh + shells + redundant stores
     assert F.dram_model(keep, rec, 32)[0] == pytest.approx(32 * 100 / 64)
     assert F.dram_model(lose, rec, 32)[0] == pytest.approx(32 * (100 + 50 + 10) / 64)
+
+
+def test_lattice_probe_layout_covers_every_access():
+    # the access-table probe's arrays (paper_2204_14242_amd/fit/measure.py):
+    # every field's first point starts a 128-byte line (the model's alignment
+    # 0), and every access of every lattice point stays inside its field
+    import torch
+    from paper_2204_14242_amd.fit import measure
+    acc, nf = measure.lbm_table()
+    nx, ny, nz = 12, 8, 6
+    a = measure.lattice_arrays(torch, torch.device("cpu"), (acc, nf), nx, ny, nz)
+    base = a["store"].data_ptr()
+    n = nx * ny * nz
+    stride = a["store"].numel() // nf
+    ld = [x for x in acc if not x[1]]
+    st = sorted({x[0] for x in acc if x[1]})
+    ins = a["in"].tolist()
+    assert a["n_ld"] == len(ld) == 100 and a["n_st"] == len(st) == 50
+    assert a["out"].tolist() == [base + 8 * (f * stride + (ins[0] - base) // 8 % stride) for f in st]
+    for slot, off, (f, _, dx, dy, dz) in zip(a["ld_field"].tolist(), a["ld_off"].tolist(), ld):
+        assert off == dx + nx * (dy + ny * dz)
+        first = (ins[slot] - base) // 8                 # element index of the field's point 0
+        assert (ins[slot] - base) % 128 == 0
+        assert first // stride == f                      # the pointer names the access's field
+        lo, hi = first + off, first + n - 1 + off
+        assert f * stride <= lo and hi < (f + 1) * stride
+
+
+def test_combined_plan_keeps_both_kernels(tmp_path):
+    import json
+    from paper_2204_14242_amd.fit import measure
+    measure.combined_plan(str(tmp_path / "p.json"))
+    cfgs = json.load(open(tmp_path / "p.json"))["configs"]
+    kinds = [c["kernel"] for c in cfgs]
+    assert kinds.count("star25") == 114 and kinds.count("lbm") == 72
+    assert all(c["fold"] == [1, 1] for c in cfgs if c["kernel"] == "lbm")
