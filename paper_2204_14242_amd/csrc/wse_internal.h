@@ -12,10 +12,11 @@ namespace wse {
 enum { T_BSEC = 0, T_BLINE = 1, T_WSEC = 2, T_WLINE = 3, T_LLINE = 4, N_TABLES = 5 };
 // thread sets evaluated for one configuration
 enum { PASS_B = 0, PASS_W = 1, PASS_L = 2, PASS_WS = 3, PASS_WR = 4, PASS_LR = 5 };
-// PASS_WR and PASS_LR fill the wave and layer sets of lattice kernels on
-// bitmaps from the address interval each instruction covers along a whole
-// thread row (row ranges), instead of thread by thread
-// PASS_W and PASS_L take their blocks' threads in row order and fill the
+// PASS_WR and PASS_LR fill the wave and layer sets on bitmaps from the
+// address interval each instruction covers along a thread row, or a block's
+// piece of it (row ranges), instead of thread by thread
+// PASS_W and PASS_L take their blocks' threads in row order (or, in the
+// general kernel where thread rows are short, block order) and fill the
 // sets; PASS_WS takes the wave's threads warp by warp for the warp-level
 // store sectors of the wave
 // insert semantics of a table entry's payload bits
@@ -131,8 +132,8 @@ struct Cfg {
     int64_t wsy, wsz, wabase;
     int32_t multidim, nsec;    // nsec: the hardware's L2 sections (>= 1)
     int64_t evals[3];           // thread x instruction evaluations per pass (upper bound)
-    int64_t l_units;            // layer pass: segments of its blocks' threads in row order
-    int64_t w_units;            // wave pass: segments of its blocks' threads in row order
+    int64_t l_units;            // layer pass: segments of its blocks' threads (row or block order)
+    int64_t w_units;            // wave pass: segments of its blocks' threads (row or block order)
     int64_t w_rows, l_rows;     // thread rows of the wave and layer passes' blocks
     int64_t s_lo, s_hi;         // lattice kernels of one element size: smallest and largest
                                 // instruction byte offset (align + elem * c0); s_lo > s_hi if unknown
