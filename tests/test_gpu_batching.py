@@ -151,3 +151,28 @@ def test_rank_of_spaces_larger_than_a_chunk(small_ctx, orc):
     want, wrank = run_oracle(orc, specs)
     assert len(set(want["perf"].tolist())) < 200
     assert_same(got, want, grank, wrank, "ranks across chunks")
+
+
+def test_configurations_larger_than_the_arena(orc):
+    # a 64 MiB arena with hash tables only: the wave of the 1024^3 stencil's
+    # 1024-thread blocks spans 9 planes of 8 MiB, more table bytes than the
+    # whole arena, and reports WSE_ENOMEM; the small domain's configurations
+    # of the same call run and match the oracle
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_2204_14242_amd import wsest
+    k = W.star_stencil(4)
+    small = W.lattice_space([(32, 32, 32)], min_threads=64, max_threads=1024, elems=[8])
+    small["explicit"] = list(range(0, len(shapes_in(64, 1024)), 4))
+    big = W.lattice_space([(1024, 1024, 1024)], min_threads=1024, max_threads=1024, elems=[8])
+    big["explicit"] = [0, 5, 10, 30, 65]
+    with wsest.Context(0, arena_bytes=64 << 20) as c:
+        c.set_tuning(bitmap_log2=0)
+        kid, hid = c.register_kernel(k), c.register_hw(W.HW1)
+        say(f"case oversized tables: {len(small['explicit'])} + {len(big['explicit'])} configurations, 64 MiB arena")
+        got, _ = c.estimate([(kid, hid, small), (kid, hid, big)], mode=wsest.BATCHED)
+    n = len(small["explicit"])
+    assert (got["status"][n:] == wsest.WSE_ENOMEM).all()
+    assert (got["status"][:n] == 0).all()
+    want, _ = run_oracle(orc, [(k, W.HW1, small)])
+    assert_same(got[:n], want, label="configurations that fit")
