@@ -277,7 +277,7 @@ wse_status wse_estimate(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces,
  * until the process ends.  Rounds are launched directly, not replayed from
  * captured graphs.  The kernel and hardware tables must be registered
  * beforehand (registration allocates).
- * Limits: the request's records (about 1.4 KiB per configuration, plus its
+ * Limits: the request's records (about 1.5 KiB per configuration, plus its
  * spaces and folding expansions) must leave at least 16 MiB of the array
  * for tables, else WSE_ENOMEM and nothing runs; a configuration whose
  * tables exceed what is left gets status WSE_ENOMEM, as one exceeding the
