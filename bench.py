@@ -104,6 +104,8 @@ def parse():
                         "rate (0 = skip)")
     p.add_argument("--serve-fractions", default="0.3,0.6,0.9",
                    help="arrival rates of the served sweep, as fractions of the served capacity")
+    p.add_argument("--serve-inflight", type=int, default=64,
+                   help="requests the server admits at once in the served legs")
     p.add_argument("--autotune-sample", type=int, default=256,
                    help="configurations of the workload the autotuner times (0 = hand-set defaults)")
     return p.parse_args()
@@ -159,7 +161,7 @@ def plain_vs_batched(ctx, kid, hid, space, n, sample):
             "batched_over_plain": rates["batched"] / rates["plain"], "identical": True}
 
 
-def served(ctx, n_requests, offered_configs_per_s=None):
+def served(ctx, n_requests, offered_configs_per_s=None, max_inflight=64):
     """Replay the first requests of the seeded Poisson trace (200 requests/s,
     sizes log-uniform 10..50,000, three kernel families, three HW sets)
     through the continuous-batching server, open loop.  With
@@ -183,7 +185,7 @@ def served(ctx, n_requests, offered_configs_per_s=None):
         scale = (total / offered_configs_per_s) / max(reqs[-1]["t_arrival"], 1e-9)
         for r in reqs:
             r["t_arrival"] *= scale
-    srv = wsest.Server(ctx, memory_budget_bytes=8 << 30, max_inflight=8)
+    srv = wsest.Server(ctx, memory_budget_bytes=8 << 30, max_inflight=max_inflight)
     tickets = []
     try:
         t0 = time.perf_counter_ns()    # CLOCK_MONOTONIC, the server's clock
@@ -212,7 +214,7 @@ def served(ctx, n_requests, offered_configs_per_s=None):
     return out
 
 
-def served_legs(ctx, n_requests, fractions):
+def served_legs(ctx, n_requests, fractions, max_inflight=64):
     """The trace at its own 200 requests/s (offered load far above capacity:
     latencies are queueing), then at fractions of the capacity measured
     there.  The server runs with row ranges (exact; byte-identical results),
@@ -221,12 +223,13 @@ def served_legs(ctx, n_requests, fractions):
     base = ctx.tuning()
     try:
         ctx.set_tuning(row_ranges=1)
-        backlog = served(ctx, n_requests)
-        sweep = [dict(served(ctx, n_requests, offered_configs_per_s=f * backlog["configs_per_s"]),
+        backlog = served(ctx, n_requests, max_inflight=max_inflight)
+        sweep = [dict(served(ctx, n_requests, offered_configs_per_s=f * backlog["configs_per_s"],
+                             max_inflight=max_inflight),
                       capacity_fraction=f) for f in fractions]
     finally:
         ctx.set_tuning(**base)
-    return {"tuning": "row_ranges=1, other parameters as the headline",
+    return {"tuning": "row_ranges=1, other parameters as the headline", "max_inflight": max_inflight,
             "latency": "completion - scheduled arrival (open loop, seed-4 trace)",
             "at_200_rps": backlog, "sweep": sweep}
 
@@ -476,7 +479,7 @@ def main():
         line["workloads"] = other_workloads(ctx, dev, skip=a.workload)
     if a.serve_requests > 0:
         fr = [float(v) for v in a.serve_fractions.split(",") if v]
-        line["served"] = served_legs(ctx, a.serve_requests, fr)
+        line["served"] = served_legs(ctx, a.serve_requests, fr, max_inflight=a.serve_inflight)
     if not a.no_cpu_baseline and len(specs) == 1:
         line["cpu_baseline"] = cpu_baseline(kernel, hw, space, per_config_evals, a.cpu_budget_s)
     print(json.dumps(line), flush=True)
