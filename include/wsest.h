@@ -51,7 +51,12 @@ typedef struct wse_ctx wse_ctx;
 typedef struct wse_server wse_server;
 
 /* Create a context on HIP device `device` with a device arena of
- * `arena_bytes` (0 = a default of 4 GiB).  *out receives the context. */
+ * `arena_bytes` (0 = a default of 4 GiB).  *out receives the context.
+ * (Debugging aid: a context created while the environment variable
+ * WSE_DEBUG_MAX_TABLE_LOG2 holds n in 5..32 caps every hash table at 2^n
+ * slots, so that table overflow can be forced from the host; inserts into a
+ * full table give up after one pass over it and the configuration reports
+ * WSE_ENOMEM as its status.) */
 wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out);
 /* Destroy a context; stops its server if one is running. */
 void wse_ctx_destroy(wse_ctx* ctx);

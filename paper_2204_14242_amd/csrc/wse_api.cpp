@@ -277,6 +277,9 @@ struct wse_ctx {
     int lds_slots = 2048;
     int table_slack = 1;
     int bitmap_log2 = 8;
+    // WSE_DEBUG_MAX_TABLE_LOG2 (read at creation): hash tables of at most
+    // 2^n slots, so that a test can force table overflow (0 = off)
+    int debug_max_log2cap = 0;
     int row_ranges = 0;
     int groups_per_cu = 128;
     int64_t target_evals = 1 << 19;
@@ -338,6 +341,10 @@ wse_status wse_ctx_create(int32_t device, size_t arena_bytes, wse_ctx** out)
     wse_ctx* c = new (std::nothrow) wse_ctx();
     if (!c) return fail(WSE_ENOMEM, "host allocation failed");
     c->device = device;
+    if (const char* v = std::getenv("WSE_DEBUG_MAX_TABLE_LOG2")) {
+        const int n_cap = std::atoi(v);
+        c->debug_max_log2cap = n_cap >= 5 && n_cap <= 32 ? n_cap : 0;
+    }
     c->arena_bytes = arena_bytes ? arena_bytes : ((size_t)4 << 30);
     c->arena_bytes = (c->arena_bytes + 255) & ~(size_t)255;
     hipError_t e = hipMalloc((void**)&c->arena, c->arena_bytes);
@@ -872,7 +879,7 @@ static wse_status job_prepare(wse_ctx* c, Job& j, hipStream_t st, size_t arena_b
     HIP_TRY(j.d_sorted.reserve(j.total));
     HIP_TRY(hipMemcpyAsync(j.d_cfg_space.p, cfg_space.data(), j.total * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(launch_decode(j.d_cfgs.p, j.total, dev_tables(c, j.d_spaces.p, n_spaces, j.exp_tab),
-                          c->table_slack, c->bitmap_log2, st));
+                          c->table_slack, c->bitmap_log2, c->debug_max_log2cap, st));
     HIP_TRY(launch_fill_zero(j.d_ctr.p, j.total * (int64_t)sizeof(Counters), st));
     j.cfgs.resize(j.total);
     HIP_TRY(hipMemcpyAsync(j.cfgs.data(), j.d_cfgs.p, j.total * sizeof(Cfg), hipMemcpyDeviceToHost, st));

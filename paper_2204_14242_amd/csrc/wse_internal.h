@@ -237,7 +237,7 @@ struct ExpandJob {
 };
 
 hipError_t launch_expand(const ExpandJob* jobs_dev, int n_jobs, DevTables t, hipStream_t s);
-hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2, int bitmap_log2,
+hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2, int bitmap_log2, int max_log2cap,
                          hipStream_t s);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t s);
 // round launches: sizes come from the device-resident RoundDesc

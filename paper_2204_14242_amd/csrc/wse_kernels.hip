@@ -412,15 +412,17 @@ __device__ void unit_range(const Cfg& c, const KernelDev& K, const Expansion* X,
 
 // capacity of a table for at most `bound` keys: the next power of two at or
 // above bound << slack (load factor at most 2^-slack)
-__device__ int64_t round_cap(int64_t bound, int slack, int* log2cap)
+__device__ int64_t round_cap(int64_t bound, int slack, int* log2cap, int max_log2cap = 0)
 {
     uint64_t want = (uint64_t)(bound > 32 ? bound : 32) << slack;
     int l = bits_for(want - 1);
+    // a host-set cap (failure injection: inserts past it report overflow)
+    if (max_log2cap > 0 && l > max_log2cap) l = max_log2cap;
     *log2cap = l;
     return (int64_t)1 << l;
 }
 
-__global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitmap_log2)
+__global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitmap_log2, int max_log2cap)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -673,7 +675,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
             break;
         }
         int64_t bound = (int64_t)keys < ev[q] ? (int64_t)keys : ev[q];
-        round_cap(bound, slack, &l2_of[q]);
+        round_cap(bound, slack, &l2_of[q], max_log2cap);
         if (l2_of[q] > 32) {
             bad = 2;
             break;
@@ -795,7 +797,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
             const uint64_t pkeys = (uint64_t)K.n_fields * (uint64_t)c.pspan;
             const int64_t bound = pkeys < (uint64_t)c.evals[PASS_W] ? (int64_t)pkeys : c.evals[PASS_W];
             int l2p = 0;
-            round_cap(bound, slack, &l2p);
+            round_cap(bound, slack, &l2p, max_log2cap);
             if (l2p > 32) {
                 bad = 2;
             } else {
@@ -819,7 +821,7 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
         const uint64_t ukeys = (uint64_t)K.n_fields * (uint64_t)c.tab[T_WSEC].span;
         const int64_t bound = ukeys < (uint64_t)c.evals[PASS_W] ? (int64_t)ukeys : c.evals[PASS_W];
         int l2u = 0;
-        round_cap(bound, slack, &l2u);
+        round_cap(bound, slack, &l2u, max_log2cap);
         if (l2u > 32) {
             bad = 2;
         } else {
@@ -848,13 +850,13 @@ __global__ void k_decode(Cfg* cfgs, int64_t n, DevTables t, int slack, int bitma
     cfgs[i] = c;
 }
 
-hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2, int bitmap_log2,
+hipError_t launch_decode(Cfg* cfgs, int64_t n, DevTables t, int table_slack_log2, int bitmap_log2, int max_log2cap,
                          hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     int64_t blocks = (n + 127) / 128;
     hipLaunchKernelGGL(k_decode, dim3((unsigned)blocks), dim3(128), 0, s, cfgs, n, t, table_slack_log2,
-                       bitmap_log2);
+                       bitmap_log2, max_log2cap);
     return hipGetLastError();
 }
 

@@ -176,3 +176,31 @@ def test_configurations_larger_than_the_arena(orc):
     assert (got["status"][:n] == 0).all()
     want, _ = run_oracle(orc, [(k, W.HW1, small)])
     assert_same(got[:n], want, label="configurations that fit")
+
+
+def test_forced_table_overflow(orc, monkeypatch):
+    # failure injection from the host: hash tables capped at 2^10 slots
+    # (WSE_DEBUG_MAX_TABLE_LOG2, read when a context is created).  The 64^3
+    # stencil's wave holds tens of thousands of sector keys: its inserts find
+    # the table full, give up after one pass over it, and the configuration
+    # reports WSE_ENOMEM; the 8^3 domain's few hundred keys fit, and those
+    # configurations of the same call match the oracle
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_2204_14242_amd import wsest
+    k = W.star_stencil(4)
+    small = W.lattice_space([(8, 8, 8)], min_threads=32, max_threads=512, elems=[8])
+    small["explicit"] = list(range(0, len(shapes_in(32, 512)), 7))
+    big = W.lattice_space([(64, 64, 64)], min_threads=256, max_threads=256, elems=[8])
+    big["explicit"] = [0, 7, 14, 27]
+    monkeypatch.setenv("WSE_DEBUG_MAX_TABLE_LOG2", "10")
+    with wsest.Context(0, arena_bytes=1 << 30) as c:
+        c.set_tuning(bitmap_log2=0)
+        kid, hid = c.register_kernel(k), c.register_hw(W.HW1)
+        say(f"case forced overflow: {len(small['explicit'])} + {len(big['explicit'])} configurations, 2^10 slots")
+        got, _ = c.estimate([(kid, hid, small), (kid, hid, big)], mode=wsest.BATCHED)
+    n = len(small["explicit"])
+    assert (got["status"][n:] == wsest.WSE_ENOMEM).all()
+    assert (got["status"][:n] == 0).all()
+    want, _ = run_oracle(orc, [(k, W.HW1, small)])
+    assert_same(got[:n], want, label="configurations whose tables fit")
