@@ -8,6 +8,8 @@ import random
 
 import numpy as np
 import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
 
 from paper_2204_14242_amd import workloads as W
 from helpers import TINY_HW, with_hw
@@ -91,7 +93,12 @@ def brute_counts(kernel, hw, shape, outer, fy, fz, elem):
                             for e in exprs if not e[1]})
     out["lines_ld_B"] = len({(e[0], addr(e, b, t) // Lb) for (_, b, t, _) in valid_B
                              for e in exprs if not e[1]})
+    # an L2 of `nsec` sections: block k caches in section k mod nsec, so the
+    # wave and layer sets hold (field, section, unit) triples
+    nsec = max(1, hw.get("l2_sections", 1))
+    page = hw.get("page_bytes", 0)
     fpld, fpst, lw, up_st = set(), set(), set(), 0
+    union_ld, pages = set(), set()
     nvalid = 0
     for k in range(w0, w1):
         up_st += warp_sector_sum(k, True)
@@ -101,10 +108,15 @@ def brute_counts(kernel, hw, shape, outer, fy, fz, elem):
             nvalid += 1
             for e in exprs:
                 a = addr(e, b, t)
-                (fpst if e[1] else fpld).add((e[0], a // S))
-                lw.add((e[0], a // Lb))
+                (fpst if e[1] else fpld).add((e[0], k % nsec, a // S))
+                lw.add((e[0], k % nsec, a // Lb))
+                if not e[1]:
+                    union_ld.add((e[0], a // S))
+                if page:
+                    pages.add((e[0], a // page))
     out.update(fpld_W=len(fpld), comp_st_W=len(fpst), lines_W=len(lw), up_st_W=up_st,
-               lups_W=nvalid * fy * fz, blocks_W=w1 - w0)
+               lups_W=nvalid * fy * fz, blocks_W=w1 - w0,
+               dup_W=len(fpld) - len(union_ld) if nsec > 1 else 0, pages_W=len(pages))
     sd = []
     for d in range(3):
         cands = []
@@ -128,7 +140,7 @@ def brute_counts(kernel, hw, shape, outer, fy, fz, elem):
             for (_, b, t, ok) in lanes(k):
                 if ok:
                     for e in exprs:
-                        s.add((e[0], addr(e, b, t) // unit))
+                        s.add((e[0], k % nsec, addr(e, b, t) // unit))
         return s
 
     out["lines_L"] = [len(footprint(s, Lb)) if s >= 0 else 0 for s in sd]
@@ -186,6 +198,39 @@ def test_random_lattice_matches_bruteforce(orc, seed):
          "accesses": acc, "flops_per_lup": 0.0}
     sp = W.lattice_space([(12, 8, 8), (16, 4, 8)], min_threads=4, max_threads=16,
                          fy=(1, 2), fz=(1, 2), elems=rng.choice([[], [4, 8]]), exps=range(3))
-    hw = with_hw(TINY_HW, warp_size=8, n_cu=rng.randint(1, 3), l1_group_lanes=4)
+    hw = with_hw(TINY_HW, warp_size=8, n_cu=rng.randint(1, 3), l1_group_lanes=4,
+                 l2_sections=1 + seed % 3, page_bytes=(0, 256)[seed % 2])
     sp["explicit"] = sorted(rng.sample(range(orc.space_size(k, sp)), 10))
+    check_space(orc, k, hw, sp)
+
+
+@st.composite
+def affine_cases(draw):
+    """A tiny affine kernel, hardware with or without L2 sections and pages,
+    and a space of a few block shapes and grids."""
+    nf = draw(st.integers(1, 3))
+    fields = [(draw(st.sampled_from([4, 8])), draw(st.sampled_from([0, 8, 40, -64]))) for _ in range(nf)]
+    coef = st.integers(-3, 3)
+    exprs = []
+    for _ in range(draw(st.integers(1, 5))):
+        f = draw(st.integers(0, nf - 1))
+        m = (1, 23 + f, 300 + 5 * f)
+        exprs.append((f, int(draw(st.booleans())), draw(st.integers(-30, 30)),
+                      *[draw(coef) * m[d] for d in range(3)], *[draw(coef) * m[d] for d in range(3)],
+                      *[draw(st.integers(-1, 1)) * m[d] for d in range(3)]))
+    hw = with_hw(TINY_HW, warp_size=draw(st.sampled_from([4, 8, 16])), n_cu=draw(st.integers(1, 3)),
+                 l1_group_lanes=2, l2_sections=draw(st.sampled_from([1, 2, 3])),
+                 page_bytes=draw(st.sampled_from([0, 128, 512])))
+    grid = (draw(st.integers(1, 4)), draw(st.integers(1, 3)), draw(st.integers(1, 3)))
+    sp = W.affine_space([grid], min_threads=2, max_threads=16, exps=range(3))
+    return W.affine_kernel(fields, exprs), hw, sp
+
+
+@settings(max_examples=25, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(affine_cases())
+def test_property_affine_with_sections_and_pages(orc, case):
+    # hypothesis-drawn kernels, hardware (L2 sections 1..3, pages) and spaces:
+    # every count of the oracle equals the brute force's, duplication and
+    # pages included (Sec. 4.2-4.4, Sec. 6)
+    k, hw, sp = case
     check_space(orc, k, hw, sp)
