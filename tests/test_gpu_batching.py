@@ -87,6 +87,27 @@ def test_each_space_alone_equals_the_mix(small_ctx):
         off += n
 
 
+def test_permuted_and_repeated_calls(small_ctx):
+    # the spaces in reverse order give each space the same bytes and ranks, and
+    # the same call repeated gives the same result bytes
+    from paper_2204_14242_amd import wsest
+    specs, reg = uneven_specs(small_ctx)
+    say("case batching: permuted and repeated calls")
+    fwd, frank = small_ctx.estimate(reg, mode=wsest.BATCHED)
+    again, arank = small_ctx.estimate(reg, mode=wsest.BATCHED)
+    assert fwd.tobytes() == again.tobytes() and np.array_equal(frank, arank)
+    rev, rrank = small_ctx.estimate(reg[::-1], mode=wsest.BATCHED)
+    sizes = [small_ctx.space_size(*r) for r in reg]
+    starts = np.cumsum([0] + sizes)
+    rstarts = np.cumsum([0] + sizes[::-1])
+    for i, n in enumerate(sizes):
+        j = len(sizes) - 1 - i
+        a = slice(starts[i], starts[i] + n)
+        b = slice(rstarts[j], rstarts[j] + n)
+        assert fwd[a].tobytes() == rev[b].tobytes()
+        assert np.array_equal(frank[a], rrank[b])
+
+
 def test_results_do_not_depend_on_tuning(small_ctx):
     from paper_2204_14242_amd import wsest
     specs, reg = uneven_specs(small_ctx)
