@@ -234,13 +234,16 @@ def served_legs(ctx, n_requests, fractions, max_inflight=64):
             "at_200_rps": backlog, "sweep": sweep}
 
 
-def cpu_baseline(kernel, hw, space, per_config_evals, budget_s):
+def cpu_baseline(kernel, hw, space, per_config_evals, budget_s, gpu_records=None):
     """Time the oracle, as it stands, on a seeded sample of the workload that
     follows its cost mix: the configurations are cut into cost strata
     (powers of 4 of their evaluation counts), every stratum the budget
     affords is sampled, and the oracle's evaluation rate in each stratum is
     applied to that stratum's share of the workload's evaluations (strata
-    above the largest affordable one take its rate)."""
+    above the largest affordable one take its rate).  With gpu_records (the
+    timed step's results, in canonical order), every sampled configuration's
+    oracle record is also compared with the GPU's, byte for byte, outside
+    the timed calls."""
     import numpy as np
     import oracle
     oracle.build(force=False)
@@ -254,6 +257,7 @@ def cpu_baseline(kernel, hw, space, per_config_evals, budget_s):
     cap = int(np.floor(np.log(budget_s / 5 * 2e7) / np.log(4.0)))
     levels = sorted(set(stratum.tolist()))
     rates, sample, t_all = {}, 0, 0.0
+    checked, differ = 0, []
     per_level_budget = budget_s / max(1, len([lv for lv in levels if lv <= cap]))
     for lv in levels:
         if lv > cap:
@@ -266,8 +270,12 @@ def cpu_baseline(kernel, hw, space, per_config_evals, budget_s):
             batch = sorted(int(v) for v in pick[i:i + n_threads])
             i += n_threads
             t0 = time.perf_counter()
-            oracle.estimate(kernel, hw, dict(space, explicit=batch), n_threads=n_threads)
+            want, _ = oracle.estimate(kernel, hw, dict(space, explicit=batch), n_threads=n_threads)
             t_used += time.perf_counter() - t0
+            if gpu_records is not None:
+                got = gpu_records[batch]
+                checked += len(batch)
+                differ += [b for b, g, w in zip(batch, got, want) if g.tobytes() != w.tobytes()]
             e_used += int(ev[batch].sum())
             done += len(batch)
         rates[lv] = e_used / t_used
@@ -279,7 +287,10 @@ def cpu_baseline(kernel, hw, space, per_config_evals, budget_s):
         e = float(ev[ok[stratum == lv]].sum())
         t_pred += e / rates[lv if lv in rates else top]
     n = len(ev)
+    if differ:
+        raise SystemExit(f"GPU results differ from the oracle at canonical indices {differ[:8]}")
     return {"value": n / t_pred, "unit": "configs/s", "cores": n_threads, "nproc": nproc, "kind": "oracle",
+            "checked_against_gpu": {"configs": checked, "identical": checked > 0},
             "sample": f"{sample} seeded configurations in {len(rates)} cost strata (4^k evaluations, "
                       f"k <= {cap}; {t_all:.1f} s on {n_threads} threads); each stratum's measured "
                       f"oracle rate applied to its share of the workload's {float(ev.sum()):.3g} "
@@ -484,7 +495,9 @@ def main():
         fr = [float(v) for v in a.serve_fractions.split(",") if v]
         line["served"] = served_legs(ctx, a.serve_requests, fr, max_inflight=a.serve_inflight)
     if not a.no_cpu_baseline and len(specs) == 1:
-        line["cpu_baseline"] = cpu_baseline(kernel, hw, space, per_config_evals, a.cpu_budget_s)
+        # (res: the timed steps' results, canonical order; one space, no subset)
+        line["cpu_baseline"] = cpu_baseline(kernel, hw, space, per_config_evals, a.cpu_budget_s,
+                                            gpu_records=res if not space.get("explicit") else None)
     print(json.dumps(line), flush=True)
     ctx.close()
 

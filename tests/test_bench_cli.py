@@ -49,3 +49,20 @@ def test_cpu_baseline_follows_the_cost_strata():
     assert out["kind"] == "oracle" and out["unit"] == "configs/s" and out["value"] > 0
     assert 1 <= out["cores"] <= 16 and out["cores"] <= out["nproc"]
     assert "4 cost strata" in out["sample"]
+    assert out["checked_against_gpu"] == {"configs": 0, "identical": False}   # nothing given to check
+
+
+def test_cpu_baseline_checks_the_given_records():
+    # the sampled configurations' oracle records against records in canonical
+    # order (here the oracle's own, standing in for the GPU's)
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    import oracle
+    from paper_2204_14242_amd import workloads as W
+    k, hw, sp = W.stencil_plain()
+    sp = dict(sp, domains=[(32, 32, 32)])
+    recs, _ = oracle.estimate(k, hw, sp, n_threads=4)
+    evals = np.array([4 ** (5 + i % 4) for i in range(len(recs))], dtype=np.float64)
+    out = bench.cpu_baseline(k, hw, sp, evals, budget_s=2.0, gpu_records=recs)
+    assert out["checked_against_gpu"]["identical"] and out["checked_against_gpu"]["configs"] > 20
