@@ -378,7 +378,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the estimator's configuration "
-              "spaces would shard by configuration range across GPUs, which this build does not do",
+              "spaces would shard by configuration range across GPUs, which this program does not do",
               file=sys.stderr)
         sys.exit(2)
     # one progress line per arena round on stderr, so long steps keep printing
