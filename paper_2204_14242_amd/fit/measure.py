@@ -137,6 +137,20 @@ def combined_plan(path):
     json.dump(plan, open(path, "w"), indent=0)
 
 
+def transition_plan(path):
+    """The combined plan with a denser sweep through the layer-condition
+    transition: x = y from 256 to 768 in steps of 32 at constant volume, six
+    1024-thread shapes of growing z extent each (102 more star-stencil
+    configurations, where the fitted overlap functions matter most)."""
+    combined_plan(path)
+    plan = json.load(open(path))
+    for x in range(256, 769, 32):
+        z = int(round(512 * 1024 * 1024 / (x * x)))
+        for s in ((512, 2, 1), (256, 2, 2), (128, 2, 4), (64, 2, 8), (32, 2, 16), (16, 2, 32)):
+            plan["configs"].append({"domain": [x, x, z], "shape": list(s), "fold": [1, 1], "kernel": "star25"})
+    json.dump(plan, open(path, "w"), indent=0)
+
+
 def default_plan(path):
     """The measured configurations: 48 block shapes of 64..1024 threads on
     256^3 (L1 and short layer sets), and the constant-volume domain-size scan
@@ -160,5 +174,7 @@ if __name__ == "__main__":
         lbm_plan(sys.argv[2])
     elif sys.argv[1] == "plan-all":
         combined_plan(sys.argv[2])
+    elif sys.argv[1] == "plan-transition":
+        transition_plan(sys.argv[2])
     else:
         main(sys.argv[1], sys.argv[2])

@@ -96,12 +96,13 @@ HW_MI355X = make_hw(warp_size=64, n_cu=256, l1_bytes=32 * KIB, l2_bytes=4 * MIB,
 # L2 as the eight XCD L2s it is (block k caches in XCD k mod 8, where the
 # dispatcher places it) and the four hit-rate functions fitted to the
 # range-4 star stencil's measured volumes on one MI355X (fit/measure.py,
-# fit/fit.py: 114 configurations of 256^3 and of the constant-volume
-# domain-size scan; median error of the DRAM volume 7 %, against 36 % for
-# one 4 MiB L2).
+# fit/fit.py: 216 configurations of 256^3 and of the constant-volume
+# domain-size scan, densely through its layer-condition transition; median
+# error of the DRAM volume 4 %, against 41 % for one 4 MiB L2; the held-out
+# LBM kernel within 7.5 %).
 HW_MI355X_FIT = dict(HW_MI355X, sector_bytes=128, l2_sections=8,
-                     fit_l1=(1.0, 0.1009, 0.03512), fit_l2_y=(0.9999, 1.448, 2.301),
-                     fit_l2_z=(0.999, 0.008391, 5.102), fit_l2_store=(0.8185, 0.0001193, 3.287))
+                     fit_l1=(1.0, 0.09735, 0.03611), fit_l2_y=(0.9126, 1.756, 1.769),
+                     fit_l2_z=(1.0, 0.002703, 6.066), fit_l2_store=(0.7516, 0.0001281, 3.255))
 
 
 # --------------------------------------------------------------------------
