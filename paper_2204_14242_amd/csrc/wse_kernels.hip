@@ -1349,14 +1349,16 @@ __device__ __forceinline__ WordProbe word_probe_seg(const PassCtx& P, uint32_t b
                                                     uint32_t kfirst)
 {
     const uint32_t w1 = act ? base + (key >> 5) + 1 : 0xffffffffu;
-    const uint32_t wfirst1 = base + (kfirst >> 5) + 1;
     const uint32_t nw1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x130, 0xf, 0xf, true);  // wave_shl:1
     const bool lead = act && nw1 != w1;
-    const uint32_t lo = w1 == wfirst1 ? (kfirst & 31) : 0u;
+    // the run's first key in this word: `kfirst` in the first word, else the
+    // word's bit 0; its bits up to `key` are a difference of two powers of
+    // two (modulo 2^32, which covers bit 31)
+    const uint32_t klo = max(kfirst, key & ~31u);
     WordProbe r;
     r.k1 = w1;
     r.lead = lead;
-    r.bits = (0xffffffffu >> (31 - (key & 31))) & (0xffffffffu << lo);
+    r.bits = (2u << (key & 31)) - (1u << (klo & 31));
     r.slot = word_slot(w1, P.wlog);
     r.old = P.wtab[r.slot];
     return r;
@@ -1385,16 +1387,19 @@ __device__ __forceinline__ void probes_issued() { asm volatile("" ::: "memory");
 __device__ __forceinline__ void word_commit(PassCtx& P, WordProbe r)
 {
     if (!r.lead) return;
+    // (a slot that holds the word holds it in its upper half, so the new
+    // content's upper half is the word in either case)
+    const unsigned long long hi = (unsigned long long)r.k1 << 32;
     unsigned long long old = r.old;
     bool mine = (uint32_t)(old >> 32) == r.k1;
-    unsigned long long want = mine ? (old | r.bits) : (((unsigned long long)r.k1 << 32) | r.bits);
+    unsigned long long want = hi | ((mine ? (uint32_t)old : 0u) | r.bits);
     if (want == old) return;
     unsigned long long prev = atomicCAS(&P.wtab[r.slot], old, want);
     // another lane or wave changed the slot first: start again from its content
     while (prev != old) {
         old = prev;
         mine = (uint32_t)(old >> 32) == r.k1;
-        want = mine ? (old | r.bits) : (((unsigned long long)r.k1 << 32) | r.bits);
+        want = hi | ((mine ? (uint32_t)old : 0u) | r.bits);
         if (want == old) return;
         prev = atomicCAS(&P.wtab[r.slot], old, want);
     }
