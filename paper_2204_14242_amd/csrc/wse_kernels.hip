@@ -1341,16 +1341,21 @@ __device__ __forceinline__ WordProbe word_probe(const PassCtx& P, uint32_t base,
 }
 
 // word_probe for a step whose keys form runs: `base` is the same on every
-// lane, the active lanes are one contiguous range and their keys rise by 0
-// or 1 from lane to lane, from `kfirst` on.  Then a run of equal words holds
-// every key between its ends, and its last lane forms the run's bits from
-// its own key and, in the first word, `kfirst`, with no scan.
+// lane, the active lanes are the contiguous range `am` (or fewer, as below)
+// and their keys rise by 0 or 1 from lane to lane, from `kfirst` on.  Then a
+// run of equal words holds every key between its ends, and its last lane
+// forms the run's bits from its own key and, in the first word, `kfirst`,
+// with no scan.  A lane of `am` without `act` (a key out of its table's
+// range: the item reports an error and its counts are void) never writes.
 __device__ __forceinline__ WordProbe word_probe_seg(const PassCtx& P, uint32_t base, bool act, uint32_t key,
-                                                    uint32_t kfirst)
+                                                    uint32_t kfirst, uint64_t am)
 {
-    const uint32_t w1 = act ? base + (key >> 5) + 1 : 0xffffffffu;
+    // every lane forms a word (an inactive lane's slot is read, but it
+    // never leads); the leads are the active lanes whose next lane holds
+    // another word, and the last lane of `am`
+    const uint32_t w1 = base + (key >> 5) + 1;
     const uint32_t nw1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)w1, 0x130, 0xf, 0xf, true);  // wave_shl:1
-    const bool lead = act && nw1 != w1;
+    const bool lead = act & __builtin_amdgcn_inverse_ballot_w64(__ballot(nw1 != w1) | ~(am >> 1));
     // the run's first key in this word: `kfirst` in the first word, else the
     // word's bit 0; its bits up to `key` are a difference of two powers of
     // two (modulo 2^32, which covers bit 31)
@@ -1373,7 +1378,7 @@ __device__ __forceinline__ WordProbe word_probe_runs(const PassCtx& P, uint32_t 
                                                      uint64_t am)
 {
     const int first = am ? __builtin_ctzll(am) : 0;
-    return word_probe_seg(P, base, act, key, (uint32_t)__builtin_amdgcn_readlane((int)key, first));
+    return word_probe_seg(P, base, act, key, (uint32_t)__builtin_amdgcn_readlane((int)key, first), am);
 }
 
 // Keeps the compiler from sinking the probes' slot reads into their commits,
@@ -1942,7 +1947,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                                     const uint32_t kfirst = (uint32_t)(((uint64_t)ubase0 +
                                                                         (uint64_t)readlane64((int64_t)ic.SL, q)) >>
                                                                        ll);
-                                    b = word_probe_seg(P, bl, actl, kl, kfirst);
+                                    b = word_probe_seg(P, bl, actl, kl, kfirst, vmask);
                                 } else {
                                     b = word_probe_runs(P, bl, actl, kl, vmask);
                                 }
