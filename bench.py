@@ -422,7 +422,7 @@ def main():
     for i in range(a.warmup):
         ctx.estimate(specs, mode=mode, out=out, rank=rank, stream=stream)
         print(f"warmup {i} done", file=sys.stderr, flush=True)
-    eval_ms, dl_ms, dl_evals, dl_launches = 0.0, 0.0, 0, 0
+    eval_ms, dl_ms, dl_evals, dl_launches, dl_skipped = 0.0, 0.0, 0, 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
@@ -433,6 +433,7 @@ def main():
         dl_ms += tm[4]
         dl_evals += st["lattice_bitmap_evals"]
         dl_launches += st["lattice_bitmap_launches"]
+        dl_skipped += st["skipped_evals"]
         print(f"step {i} done: stages ms {[round(v, 1) for v in tm[:5]]}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -444,14 +445,17 @@ def main():
     n_ok = int((res["status"] == 0).sum())
     # the dominant kernel: the lattice bitmap evaluation launch (wave and
     # layer passes of lattice kernels whose sets are bitmaps), timed with HIP
-    # events on its own stream; the whole evaluation phase for context
-    phase = OPS_PER_EVAL * evals / (eval_ms / 1e3) / 1e12 if eval_ms > 0 else 0.0
+    # events on its own stream; the whole evaluation phase for context.  Both
+    # are charged for the evaluations performed: the modelled (thread,
+    # instruction) pairs less those of layer steps left out because their run
+    # of line keys repeats the step's before them (they could add nothing).
+    phase = OPS_PER_EVAL * (evals - dl_skipped) / (eval_ms / 1e3) / 1e12 if eval_ms > 0 else 0.0
     if dl_launches > 0 and dl_ms > 0:
         kname = "k_eval<true> (wave and layer passes of lattice kernels on bitmaps)"
-        k_evals, k_ms, k_launches = dl_evals, dl_ms, dl_launches
+        k_evals, k_skipped, k_ms, k_launches = dl_evals - dl_skipped, dl_skipped, dl_ms, dl_launches
     else:
         kname = "k_eval (all evaluation launches of a round)"
-        k_evals, k_ms, k_launches = evals, eval_ms, max(st["rounds"] * a.steps, 1)
+        k_evals, k_skipped, k_ms, k_launches = evals - dl_skipped, dl_skipped, eval_ms, max(st["rounds"] * a.steps, 1)
     achieved = OPS_PER_EVAL * k_evals / (k_ms / 1e3) / 1e12
     useful = USEFUL_OPS_PER_EVAL * k_evals / (k_ms / 1e3) / 1e12
     line = {
@@ -479,6 +483,7 @@ def main():
                      "kernel": kname, "avg_launch_ms": k_ms / k_launches,
                      "lane_ops_per_launch": OPS_PER_EVAL * k_evals / k_launches,
                      "evaluations_per_launch": k_evals / k_launches,
+                     "evaluations_skipped_per_launch": k_skipped / k_launches,
                      "ops_per_eval": OPS_PER_EVAL,
                      "frac_address_and_key_only": useful / VALU_PEAK_TOPS,
                      "evaluation_phase": {"achieved": phase, "frac": phase / VALU_PEAK_TOPS,

@@ -396,14 +396,16 @@ wse_status wse_rhat(wse_ctx* ctx, const wse_fit* fit, const double* O, double* R
  * on their own stream).  `n` entries (<= 8) are copied. */
 wse_status wse_last_timings(const wse_ctx* ctx, double* ms, int32_t n);
 
-/* Work statistics of the last wse_estimate call on this context (n <= 9
- * entries): [0] (thread, instruction) address evaluations performed over all
- * thread sets, [1] table bytes used (hash tables and bitmaps), [2]
+/* Work statistics of the last wse_estimate call on this context (n <= 10
+ * entries): [0] (thread, instruction) address evaluations over all thread
+ * sets, [1] table bytes used (hash tables and bitmaps), [2]
  * evaluation-kernel launches, [3] arena rounds, [4] configurations
  * evaluated, [5] configurations with sets kept as bitmaps, [6] evaluations
- * performed by the lattice bitmap launches, [7] their number, [8] thread
- * rows whose wave and layer sets were filled by row ranges (0 unless the
- * tuning's row_ranges is 1). */
+ * of the lattice bitmap launches, [7] their number, [8] thread rows whose
+ * wave and layer sets were filled by row ranges (0 unless the tuning's
+ * row_ranges is 1), [9] evaluations of [6] left out because they could add
+ * nothing: those of a layer-pass step over one thread row whose run of line
+ * keys is the step's before it (the same keys of the same bitmap). */
 wse_status wse_last_stats(wse_ctx* ctx, int64_t* stats, int32_t n);
 
 /* Address evaluations the last wse_estimate call performed for each of its

@@ -1386,13 +1386,15 @@ extern "C" wse_status wse_last_stats(wse_ctx* c, int64_t* stats, int32_t n)
     int64_t evals = 0;
     for (int64_t i = 0; i < c->last_total; i++)
         evals += (int64_t)(c->last_ctr[i].lanes_B + c->last_ctr[i].lanes_W + c->last_ctr[i].lanes_L) * c->last_E[i];
-    int64_t dl_evals = 0;
-    for (int64_t i = 0; i < c->last_total; i++)
+    int64_t dl_evals = 0, skipped = 0;
+    for (int64_t i = 0; i < c->last_total; i++) {
         if (c->last_dl[i])
             dl_evals += (int64_t)(c->last_ctr[i].lanes_W + c->last_ctr[i].lanes_L) * c->last_E[i];
-    int64_t v[9] = {evals, c->last_table_bytes, c->last_launches, c->last_rounds, c->last_total, c->last_dense,
-                    dl_evals, c->last_dl_launches, c->last_row_units};
-    for (int i = 0; i < n && i < 9; i++) stats[i] = v[i];
+        skipped += (int64_t)c->last_ctr[i].skip_L;
+    }
+    int64_t v[10] = {evals, c->last_table_bytes, c->last_launches, c->last_rounds, c->last_total, c->last_dense,
+                     dl_evals, c->last_dl_launches, c->last_row_units, skipped};
+    for (int i = 0; i < n && i < 10; i++) stats[i] = v[i];
     return WSE_OK;
 }
 

@@ -179,57 +179,71 @@ __global__ void k_expand_mark(const ExpandJob* jobs, DevTables t)
     J.scratch_keep[c] = keep;
 }
 
-// stable compaction of the kept candidates; one workgroup per job
+// Expanded instruction of candidate c = (access a, fold offsets r / fz, r % fz).
+__device__ __forceinline__ ExprL expand_candidate(const AccessL* acc, int a, int ry, int rz)
+{
+    ExprL e;
+    e.f = acc[a].f;
+    e.st = acc[a].st;
+    e.v[0] = acc[a].o[0];
+    e.v[1] = acc[a].o[1] + ry;
+    e.v[2] = acc[a].o[2] + rz;
+    e.pad = 0;
+    return e;
+}
+
+// The order of the expansion: field, then z, y and x offset, then loads
+// before stores.  Instructions that differ only in x come one after another,
+// so a wave's consecutive steps often touch the same run of lines.
+__device__ __forceinline__ bool expr_before(const ExprL& p, const ExprL& q)
+{
+    if (p.f != q.f) return p.f < q.f;
+    if (p.v[2] != q.v[2]) return p.v[2] < q.v[2];
+    if (p.v[1] != q.v[1]) return p.v[1] < q.v[1];
+    if (p.v[0] != q.v[0]) return p.v[0] < q.v[0];
+    return p.st < q.st;
+}
+
+// The kept candidates in the order of expr_before; one workgroup per job.
+// No two kept candidates are equal in that order (the duplicate test above
+// compares the same fields), so each one's rank among them is its position.
 __global__ void k_expand_compact(const ExpandJob* jobs, DevTables t)
 {
     const ExpandJob& J = jobs[blockIdx.x];
     const KernelDev& K = t.kernels[J.kernel_id];
     const AccessL* acc = (const AccessL*)K.items;
-    int ff = J.fy * J.fz;
-    int n = K.n_items * ff;
-    __shared__ int scan[1024];
-    __shared__ int base_s;
-    if (threadIdx.x == 0) base_s = 0;
-    __syncthreads();
-    int n_ld = 0;
-    for (int c0 = 0; c0 < n; c0 += 1024) {
-        int c = c0 + (int)threadIdx.x;
-        int k = c < n ? J.scratch_keep[c] : 0;
-        scan[threadIdx.x] = k;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            int v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
-            __syncthreads();
-            scan[threadIdx.x] += v;
-            __syncthreads();
-        }
-        int base = base_s;
-        if (k) {
-            int a = c / ff, r = c % ff;
-            ExprL e;
-            e.f = acc[a].f;
-            e.st = acc[a].st;
-            e.v[0] = acc[a].o[0];
-            e.v[1] = acc[a].o[1] + r / J.fz;
-            e.v[2] = acc[a].o[2] + r % J.fz;
-            e.pad = 0;
-            J.out[base + scan[threadIdx.x] - 1] = e;
-            if (!e.st) n_ld++;
-        }
-        __syncthreads();
-        if (threadIdx.x == 1023) base_s = base + scan[1023];
-        __syncthreads();
+    const int ff = J.fy * J.fz;
+    const int n = K.n_items * ff;
+    int n_keep = 0, n_ld = 0;
+    for (int c = (int)threadIdx.x; c < n; c += (int)blockDim.x) {
+        if (!J.scratch_keep[c]) continue;
+        const int r = c % ff;
+        const ExprL e = expand_candidate(acc, c / ff, r / J.fz, r % J.fz);
+        int rank = 0;
+        for (int a = 0, d = 0; a < K.n_items; a++)
+            for (int ry = 0; ry < J.fy; ry++)
+                for (int rz = 0; rz < J.fz; rz++, d++)
+                    if (J.scratch_keep[d] && expr_before(expand_candidate(acc, a, ry, rz), e)) rank++;
+        J.out[rank] = e;
+        n_keep++;
+        if (!e.st) n_ld++;
     }
-    // loads among the kept instructions
-    for (int off = 32; off >= 1; off >>= 1) n_ld += __shfl_xor(n_ld, off);
-    __shared__ int nld_s;
-    if (threadIdx.x == 0) nld_s = 0;
+    // totals over the workgroup
+    for (int off = 32; off >= 1; off >>= 1) {
+        n_keep += __shfl_xor(n_keep, off);
+        n_ld += __shfl_xor(n_ld, off);
+    }
+    __shared__ int keep_s, nld_s;
+    if (threadIdx.x == 0) keep_s = nld_s = 0;
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) atomicAdd(&nld_s, n_ld);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&keep_s, n_keep);
+        atomicAdd(&nld_s, n_ld);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         J.slot->ex = J.out;
-        J.slot->E = base_s;
+        J.slot->E = keep_s;
         J.slot->n_ld = nld_s;
     }
 }
@@ -1693,7 +1707,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
     const int64_t f1 = c.fold[1], f2 = c.fold[2];
     const int64_t smin = c.smin;
     const int tag_bits = c.tag_bits;
-    int64_t acc_up_ld = 0, acc_up_st = 0, acc_cyc = 0, acc_lanes = 0, acc_warps = 0;
+    int64_t acc_up_ld = 0, acc_up_st = 0, acc_cyc = 0, acc_lanes = 0, acc_warps = 0, acc_skip = 0;
     // a lane whose key left its table's range (reported once, after the item)
     bool out_of_range = false;
     // wave and layer passes: row order, or block order (ROWORD false) where
@@ -1849,13 +1863,32 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             constexpr int MODE = decltype(mode_tag)::value;
             constexpr bool FAST = MODE >= 1;
             constexpr bool CHECK = MODE == 0;
-            _Pragma("unroll 2") for (int q = 0; q < n_in; q++) {
+            // Line-only layer steps set the keys from the first valid lane's
+            // to the last valid lane's, and no other, in the segment's one
+            // line bitmap: a step whose two keys equal those of the step
+            // before it adds nothing.  Lane q works out instruction q's two
+            // keys (as the steps do), compares them with lane q - 1's, and
+            // the loop visits only the steps left in `todo` (the plain loop
+            // where none is left out).
+            uint64_t todo = 0;
+            if constexpr (MODE == 3) {
+                const int64_t ubase_last = ubase0 + (int64_t)(__popcll(vmask) - 1) * uelem;
+                const uint32_t kf = (uint32_t)(((uint64_t)ubase0 + ic.SL) >> ll);
+                const uint32_t kz = (uint32_t)(((uint64_t)ubase_last + ic.SL) >> ll);
+                const uint32_t pf = (uint32_t)__builtin_amdgcn_mov_dpp((int)kf, 0x138, 0xf, 0xf, true);  // wave_shr:1
+                const uint32_t pz = (uint32_t)__builtin_amdgcn_mov_dpp((int)kz, 0x138, 0xf, 0xf, true);
+                const uint64_t in = n_in >= 64 ? ~0ull : ((1ull << n_in) - 1);
+                const uint64_t same = __ballot(kf == pf && kz == pz) & in & ~1ull;
+                todo = in & ~same;
+                acc_skip += (int64_t)__popcll(same) * __popcll(vmask);
+            }
+            auto step = [&](const int q) {
                 int new0 = 0, new1 = 0;
                 if (vmask) {
                     const int64_t S = readlane64(ic.S, q);
                     const int32_t m = readlane32(meta, q);
                     const int st = m & 1;
-                    if (PASS == PASS_WS && !st) continue;
+                    if (PASS == PASS_WS && !st) return;
                     int64_t addr;
                     if (FAST) {
                         addr = ubase + S;
@@ -1979,6 +2012,15 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                     }
                 }
                 if (!DENSE) step_sync<PASS>(P, new0, new1, do_sec);
+            };
+            if (MODE == 3 && todo != (n_in >= 64 ? ~0ull : ((1ull << n_in) - 1))) {
+                _Pragma("unroll 2") for (uint64_t t = todo; t;) {
+                    const int q = __builtin_ctzll(t);
+                    t &= ~(1ull << q);
+                    step(q);
+                }
+            } else {
+                _Pragma("unroll 2") for (int q = 0; q < n_in; q++) step(q);
             }
             };
             using General = std::integral_constant<int, 0>;
@@ -2041,6 +2083,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             atomicAdd(&ctr->up_st_W, (unsigned long long)acc_up_st);
         } else {
             atomicAdd(&ctr->lanes_L, (unsigned long long)acc_lanes);
+            if (acc_skip) atomicAdd(&ctr->skip_L, (unsigned long long)acc_skip);
         }
         if (P.err) atomicOr(&ctr->err, (unsigned long long)P.err);
     }

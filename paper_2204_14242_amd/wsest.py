@@ -356,12 +356,13 @@ class Context:
 
     def last_stats(self):
         """dict of the last call's work: evaluations, table bytes, launches, rounds, configs,
-        configurations kept as bitmaps"""
-        v = (C.c_int64 * 9)()
-        _check(lib().wse_last_stats(self._ctx, v, 9), self._ctx)
+        configurations kept as bitmaps, and the lattice bitmap launches' evaluations left out
+        as adding nothing"""
+        v = (C.c_int64 * 10)()
+        _check(lib().wse_last_stats(self._ctx, v, 10), self._ctx)
         return {"evals": v[0], "table_bytes": v[1], "eval_launches": v[2], "rounds": v[3],
                 "configs": v[4], "bitmap_configs": v[5], "lattice_bitmap_evals": v[6],
-                "lattice_bitmap_launches": v[7], "row_range_units": v[8]}
+                "lattice_bitmap_launches": v[7], "row_range_units": v[8], "skipped_evals": v[9]}
 
     def last_evals(self, n):
         """address evaluations of each configuration of the last call"""
