@@ -3,8 +3,8 @@
 Calls only the CPU oracle (oracle/) on the seeded workloads; run from the
 repository root:
 
-    python tests/golden/make_golden.py [stencil_plain|stencil_batched|lbm|stress|all]
-                                       [--threads N]
+    python tests/golden/make_golden.py [stencil_plain|stencil_batched|stencil_fit|lbm|
+                                        stress|all] [--threads N]
 
 Files written next to this script:
 - stencil_plain_256.npz: the whole 230-configuration space of the range-4
@@ -12,7 +12,10 @@ Files written next to this script:
 - stencil_batched_sample.npz, lbm_batched_sample.npz, stress_sample.npz:
   seeded stratified samples of the large spaces (about 2 % of the stencil and
   LBM spaces, stratified per domain and folding, plus each large domain's
-  heaviest configurations; 10 configurations from each of 210 stress spaces).
+  heaviest configurations; 10 configurations from each of 210 stress spaces);
+- stencil_fit_sample.npz: the same kind of sample of the stencil space on
+  the fitted MI355X description (eight L2 sections, 128-byte transfer units,
+  the fitted hit-rate functions) with 4 KiB translation pages.
 
 A sample is a list of "chunks".  Each chunk is one explicit subset of one
 space and one oracle call, so its ranks are ranks within that subset; the
@@ -162,6 +165,22 @@ def make_stencil_batched(threads):
     np.savez(os.path.join(HERE, "stencil_batched_sample.npz"), **out)
 
 
+def stencil_fit_hw():
+    """The fitted MI355X description with 4 KiB translation pages."""
+    return dict(W.HW_MI355X_FIT, page_bytes=4096)
+
+
+def make_stencil_fit(threads):
+    k, _, sp = W.stencil_batched()
+    hw = stencil_fit_hw()
+    # 80 strata x 5 = 400 (1.0 % of 40,160), plus the three heaviest
+    # configurations of each of the 256^3, 512^3 and 1024^3 domains
+    chunks = lattice_sample(k, sp, per_stratum=5, heavy_domains=(2, 3, 4), heavy_per_domain=3,
+                            heavy_cap=float("inf"), seed=34)
+    out = run_chunks(lambda s: k, lambda s: hw, lambda s: sp, chunks, threads, "stencil_fit")
+    np.savez(os.path.join(HERE, "stencil_fit_sample.npz"), **out)
+
+
 def make_lbm(threads):
     k, hw, sp = W.lbm_batched()
     # 16 folds x 5 = 80 (2.0 % of 4,016), plus the three heaviest below the cap
@@ -187,7 +206,8 @@ def make_stress(threads):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("which", nargs="?", default="stencil_plain",
-                    choices=["stencil_plain", "stencil_batched", "lbm", "stress", "all"])
+                    choices=["stencil_plain", "stencil_batched", "stencil_fit", "lbm", "stress",
+                             "all"])
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     a = ap.parse_args()
     oracle.build()
@@ -199,6 +219,8 @@ def main():
         make_lbm(a.threads)
     if a.which in ("stencil_batched", "all"):
         make_stencil_batched(a.threads)
+    if a.which in ("stencil_fit", "all"):
+        make_stencil_fit(a.threads)
 
 
 if __name__ == "__main__":

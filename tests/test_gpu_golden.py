@@ -5,7 +5,10 @@ stratified samples of the three large workloads: about 2 % of the
 40,160-configuration stencil space and of the 4,016-configuration LBM space
 (stratified per domain and folding, plus each large domain's heaviest
 configurations, above 10^9 evaluations) and 10 configurations of each of
-210 spaces of the 10^6-configuration stress batch.  Each file holds
+210 spaces of the 10^6-configuration stress batch; and about 1 % of the
+stencil space on the fitted MI355X description (eight L2 sections, 4 KiB
+translation pages), where the sectioned footprints, the duplicated lines and
+the page counts of full-size domains meet the fitted hit-rate functions.  Each file holds
 "chunks": one explicit subset of one space per oracle call.  Here every
 chunk of a file becomes one space of a single batched estimate, in the
 benchmark's launch configuration, and every record must match byte for
@@ -73,6 +76,21 @@ def test_stencil_batched_stored_sample(ctx):
     # every domain size, and the heavy tail the benchmark's time sits in
     assert len({tuple(d) for d in got["domain"].tolist()}) == 5
     assert (evals > 1e9).sum() >= 5, sorted(evals)[-8:]
+    # layer steps whose run of line keys repeats the step's before them were
+    # left out, and the records above are still the oracle's
+    st = ctx.last_stats()
+    assert 0 < st["skipped_evals"] < st["lattice_bitmap_evals"], st
+
+
+def test_stencil_fit_stored_sample(ctx):
+    k, _, sp = W.stencil_batched()
+    hw = dict(W.HW_MI355X_FIT, page_bytes=4096)
+    got, evals = run_chunks(ctx, load("stencil_fit_sample.npz"), lambda s: (k, hw, sp),
+                            "stencil on the fitted MI355X description", 400)
+    ran = got["status"] == 0
+    assert len({tuple(d) for d in got["domain"].tolist()}) == 5
+    assert (evals > 1e9).sum() >= 5, sorted(evals)[-8:]
+    assert ran.all() and (got["pages_W"] > 0).all() and (got["dup_W"] > 0).mean() > 0.5
 
 
 def test_lbm_batched_stored_sample(ctx):
