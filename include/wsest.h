@@ -405,7 +405,8 @@ wse_status wse_last_timings(const wse_ctx* ctx, double* ms, int32_t n);
  * wave and layer sets were filled by row ranges (0 unless the tuning's
  * row_ranges is 1), [9] evaluations of [6] left out because they could add
  * nothing: those of a layer-pass step over one thread row whose run of line
- * keys is the step's before it (the same keys of the same bitmap). */
+ * keys lies inside the run of the instruction before it (keys of the same
+ * bitmap that are set already). */
 wse_status wse_last_stats(wse_ctx* ctx, int64_t* stats, int32_t n);
 
 /* Address evaluations the last wse_estimate call performed for each of its

@@ -167,7 +167,8 @@ struct Counters {
     unsigned long long pages_W;
     unsigned long long fpld_U;  // wave load sectors of all L2 sections together
     // layer (thread, instruction) pairs not evaluated: those of line-only
-    // steps whose first and last line keys equal the step's before them
+    // steps whose run of line keys lies inside the run of the instruction
+    // before them
     unsigned long long skip_L;
     unsigned long long pad;     // (a multiple of 16 bytes)
 };

@@ -1865,8 +1865,9 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             constexpr bool CHECK = MODE == 0;
             // Line-only layer steps set the keys from the first valid lane's
             // to the last valid lane's, and no other, in the segment's one
-            // line bitmap: a step whose two keys equal those of the step
-            // before it adds nothing.  Lane q works out instruction q's two
+            // line bitmap: a step whose run of keys lies inside the run of
+            // the instruction before it adds nothing (that run was set, or lies
+            // inside a run that was).  Lane q works out instruction q's two
             // keys (as the steps do), compares them with lane q - 1's, and
             // the loop visits only the steps left in `todo` (the plain loop
             // where none is left out).
@@ -1878,7 +1879,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 const uint32_t pf = (uint32_t)__builtin_amdgcn_mov_dpp((int)kf, 0x138, 0xf, 0xf, true);  // wave_shr:1
                 const uint32_t pz = (uint32_t)__builtin_amdgcn_mov_dpp((int)kz, 0x138, 0xf, 0xf, true);
                 const uint64_t in = n_in >= 64 ? ~0ull : ((1ull << n_in) - 1);
-                const uint64_t same = __ballot(kf == pf && kz == pz) & in & ~1ull;
+                const uint64_t same = __ballot(kf >= pf && kz <= pz) & in & ~1ull;
                 todo = in & ~same;
                 acc_skip += (int64_t)__popcll(same) * __popcll(vmask);
             }
