@@ -447,9 +447,9 @@ def main():
     # layer passes of lattice kernels whose sets are bitmaps), timed with HIP
     # events on its own stream; the whole evaluation phase for context.  Both
     # are charged for the evaluations performed: the modelled (thread,
-    # instruction) pairs less those of layer steps left out because their run
-    # of line keys lies inside the previous instruction's (they could add
-    # nothing).
+    # instruction) pairs less those of wave and layer steps left out because
+    # their runs of keys lie inside the previous instruction's (they could
+    # add nothing).
     phase = OPS_PER_EVAL * (evals - dl_skipped) / (eval_ms / 1e3) / 1e12 if eval_ms > 0 else 0.0
     if dl_launches > 0 and dl_ms > 0:
         kname = "k_eval<true> (wave and layer passes of lattice kernels on bitmaps)"

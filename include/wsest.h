@@ -404,9 +404,9 @@ wse_status wse_last_timings(const wse_ctx* ctx, double* ms, int32_t n);
  * of the lattice bitmap launches, [7] their number, [8] thread rows whose
  * wave and layer sets were filled by row ranges (0 unless the tuning's
  * row_ranges is 1), [9] evaluations of [6] left out because they could add
- * nothing: those of a layer-pass step over one thread row whose run of line
- * keys lies inside the run of the instruction before it (keys of the same
- * bitmap that are set already). */
+ * nothing: those of a wave- or layer-pass step over one thread row whose
+ * runs of sector and line keys lie inside the runs of the instruction before
+ * it (keys of the same bitmaps that are set already). */
 wse_status wse_last_stats(wse_ctx* ctx, int64_t* stats, int32_t n);
 
 /* Address evaluations the last wse_estimate call performed for each of its

@@ -166,9 +166,9 @@ struct Counters {
     unsigned long long lanes_L;
     unsigned long long pages_W;
     unsigned long long fpld_U;  // wave load sectors of all L2 sections together
-    // layer (thread, instruction) pairs not evaluated: those of line-only
-    // steps whose run of line keys lies inside the run of the instruction
-    // before them
+    // wave and layer (thread, instruction) pairs not evaluated: those of
+    // steps over one thread row whose runs of keys lie inside the runs of
+    // the instruction before them
     unsigned long long skip_L;
     unsigned long long pad;     // (a multiple of 16 bytes)
 };

@@ -1883,6 +1883,32 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 todo = in & ~same;
                 acc_skip += (int64_t)__popcll(same) * __popcll(vmask);
             }
+            // The same for steps with every key in range (wave pass, and
+            // layer steps whose sectors all lie in the table): a step adds
+            // nothing when its run of sector keys and its run of line keys,
+            // where it sets them, lie inside the previous instruction's runs
+            // and (wave pass) it writes the same kind's sector bitmap.
+            if constexpr (MODE == 2) {
+                const int64_t ubase_last = ubase0 + (int64_t)(__popcll(vmask) - 1) * uelem;
+                const int64_t a0 = ubase0 + ic.S, a1 = ubase_last + ic.S;
+                const uint32_t lf = (uint32_t)((a0 >> ll) - umin_l + ic.fl - 1);
+                const uint32_t lz = (uint32_t)((a1 >> ll) - umin_l + ic.fl - 1);
+                const uint32_t sf = (uint32_t)((a0 >> ls) - umin_s + ic.fs - 1);
+                const uint32_t sz = (uint32_t)((a1 >> ls) - umin_s + ic.fs - 1);
+                const uint32_t plf = (uint32_t)__builtin_amdgcn_mov_dpp((int)lf, 0x138, 0xf, 0xf, true);  // wave_shr:1
+                const uint32_t plz = (uint32_t)__builtin_amdgcn_mov_dpp((int)lz, 0x138, 0xf, 0xf, true);
+                const uint32_t psf = (uint32_t)__builtin_amdgcn_mov_dpp((int)sf, 0x138, 0xf, 0xf, true);
+                const uint32_t psz = (uint32_t)__builtin_amdgcn_mov_dpp((int)sz, 0x138, 0xf, 0xf, true);
+                const int32_t pst = __builtin_amdgcn_mov_dpp(ic.st, 0x138, 0xf, 0xf, true);
+                const bool lines = PASS == PASS_L || w_lines;
+                const bool secs = PASS == PASS_W || do_sec;
+                const bool inside = (PASS != PASS_W || ic.st == pst) && (!lines || (lf >= plf && lz <= plz)) &&
+                                    (!secs || (sf >= psf && sz <= psz));
+                const uint64_t in = n_in >= 64 ? ~0ull : ((1ull << n_in) - 1);
+                const uint64_t same = __ballot(inside) & in & ~1ull;
+                todo = in & ~same;
+                acc_skip += (int64_t)__popcll(same) * __popcll(vmask);
+            }
             auto step = [&](const int q) {
                 int new0 = 0, new1 = 0;
                 if (vmask) {
@@ -2014,7 +2040,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 }
                 if (!DENSE) step_sync<PASS>(P, new0, new1, do_sec);
             };
-            if (MODE == 3 && todo != (n_in >= 64 ? ~0ull : ((1ull << n_in) - 1))) {
+            if ((MODE == 2 || MODE == 3) && todo != (n_in >= 64 ? ~0ull : ((1ull << n_in) - 1))) {
                 _Pragma("unroll 2") for (uint64_t t = todo; t;) {
                     const int q = __builtin_ctzll(t);
                     t &= ~(1ull << q);
@@ -2080,6 +2106,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             atomicAdd(&ctr->l1_cycles_B, (unsigned long long)acc_cyc);
         } else if (PASS == PASS_W) {
             atomicAdd(&ctr->lanes_W, (unsigned long long)acc_lanes);
+            if (acc_skip) atomicAdd(&ctr->skip_L, (unsigned long long)acc_skip);
         } else if (PASS == PASS_WS) {
             atomicAdd(&ctr->up_st_W, (unsigned long long)acc_up_st);
         } else {

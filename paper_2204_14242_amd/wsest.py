@@ -357,7 +357,7 @@ class Context:
     def last_stats(self):
         """dict of the last call's work: evaluations, table bytes, launches, rounds, configs,
         configurations kept as bitmaps, and the lattice bitmap launches' evaluations left out
-        as adding nothing"""
+        as adding nothing (wave and layer steps whose runs of keys were set already)"""
         v = (C.c_int64 * 10)()
         _check(lib().wse_last_stats(self._ctx, v, 10), self._ctx)
         return {"evals": v[0], "table_bytes": v[1], "eval_launches": v[2], "rounds": v[3],
