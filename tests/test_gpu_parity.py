@@ -81,6 +81,26 @@ def test_stencil_folding_and_elements(ctx, orc):
     check(ctx, orc, [(k, W.HW1, sp)], "stencil folds/elems")
 
 
+def test_runs_inside_the_previous_left_out(ctx, orc):
+    # wave and layer steps whose runs of keys lie inside the previous
+    # instruction's are left out on bitmaps: short and ragged rows (blocks 8
+    # to 256 threads wide), both element sizes, ghost layers and an
+    # alignment that start rows mid-line, folding, and sectors as large as
+    # lines; the records stay the oracle's
+    k = W.star_stencil(4, ghost=3, align=40)
+    sp = W.lattice_space([(40, 24, 20), (72, 16, 12)], min_threads=8, max_threads=256,
+                         fy=(1, 2), fz=(1, 4), elems=[4, 8])
+    n = 2 * 2 * 2 * 2 * 155
+    sp["explicit"] = sorted(random.Random(61).sample(range(n), 40))
+    specs = [(k, W.HW1, sp), (k, with_hw(W.HW1, sector_bytes=128), sp)]
+    check(ctx, orc, specs, "runs inside the previous")
+    st = ctx.last_stats()
+    if ctx.representation == "bitmap":
+        assert 0 < st["skipped_evals"] < st["lattice_bitmap_evals"], st
+    if ctx.representation == "hash":
+        assert st["skipped_evals"] == 0, st
+
+
 def test_line_and_sector_sizes(ctx, orc):
     """Line/sector ratios of 1, 2, 8 and 128: on bitmaps the wave's lines are
     counted from its sector bitmaps up to a ratio of 32, and keep a line
