@@ -1299,6 +1299,14 @@ struct WordProbe {
 // of 4 lanes, 4 = within rows of 16, 6 = across the wave.
 constexpr int kMergeSteps = 6;
 
+// Lane l - 1's value in lane l (0 in lane 0).
+__device__ __forceinline__ int64_t dpp_shr64(int64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, 0x138, 0xf, 0xf, true);  // wave_shr:1
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)((uint64_t)v >> 32), 0x138, 0xf, 0xf, true);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ uint32_t dpp_merge(uint32_t bits, uint32_t w1, uint32_t src_bits, uint32_t src_w1)
 {
     return bits | (src_bits & (0u - (uint32_t)(src_w1 == w1)));
@@ -1883,12 +1891,16 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 todo = in & ~same;
                 acc_skip += (int64_t)__popcll(same) * __popcll(vmask);
             }
-            // The same for steps with every key in range (wave pass, and
-            // layer steps whose sectors all lie in the table): a step adds
-            // nothing when its run of sector keys and its run of line keys,
-            // where it sets them, lie inside the previous instruction's runs
-            // and (wave pass) it writes the same kind's sector bitmap.
-            if constexpr (MODE == 2) {
+            // The same for steps that set a run of sector keys and a run of
+            // line keys (wave pass, and layer steps): a step adds nothing when
+            // both runs, where it sets them, lie inside the previous
+            // instruction's runs and (wave pass) it writes the same kind's
+            // sector bitmap.  Line keys are in range here, so a line run
+            // inside another is of the same field.  Where sectors may leave
+            // the table (layer mode 1) the step sets the part of its sector
+            // run inside the table, and the runs are compared as sector
+            // indices, which do not wrap.
+            if constexpr (MODE == 1 || MODE == 2) {
                 const int64_t ubase_last = ubase0 + (int64_t)(__popcll(vmask) - 1) * uelem;
                 const int64_t a0 = ubase0 + ic.S, a1 = ubase_last + ic.S;
                 const uint32_t lf = (uint32_t)((a0 >> ll) - umin_l + ic.fl - 1);
@@ -1902,8 +1914,16 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 const int32_t pst = __builtin_amdgcn_mov_dpp(ic.st, 0x138, 0xf, 0xf, true);
                 const bool lines = PASS == PASS_L || w_lines;
                 const bool secs = PASS == PASS_W || do_sec;
+                bool secs_inside;
+                if constexpr (MODE == 2) {
+                    secs_inside = sf >= psf && sz <= psz;
+                } else {
+                    const int64_t s0 = a0 >> ls, s1 = a1 >> ls;
+                    const int64_t ps0 = dpp_shr64(s0), ps1 = dpp_shr64(s1);
+                    secs_inside = s0 >= ps0 && s1 <= ps1;
+                }
                 const bool inside = (PASS != PASS_W || ic.st == pst) && (!lines || (lf >= plf && lz <= plz)) &&
-                                    (!secs || (sf >= psf && sz <= psz));
+                                    (!secs || secs_inside);
                 const uint64_t in = n_in >= 64 ? ~0ull : ((1ull << n_in) - 1);
                 const uint64_t same = __ballot(inside) & in & ~1ull;
                 todo = in & ~same;
@@ -2040,7 +2060,7 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 }
                 if (!DENSE) step_sync<PASS>(P, new0, new1, do_sec);
             };
-            if ((MODE == 2 || MODE == 3) && todo != (n_in >= 64 ? ~0ull : ((1ull << n_in) - 1))) {
+            if (MODE >= 1 && todo != (n_in >= 64 ? ~0ull : ((1ull << n_in) - 1))) {
                 _Pragma("unroll 2") for (uint64_t t = todo; t;) {
                     const int q = __builtin_ctzll(t);
                     t &= ~(1ull << q);
