@@ -1299,11 +1299,13 @@ struct WordProbe {
 // of 4 lanes, 4 = within rows of 16, 6 = across the wave.
 constexpr int kMergeSteps = 6;
 
-// Lane l - 1's value in lane l (0 in lane 0).
-__device__ __forceinline__ int64_t dpp_shr64(int64_t v)
+// A 64-bit DPP move (wave_shr:1 = 0x138 gives lane l - 1's value in lane l,
+// wave_shl:1 = 0x130 lane l + 1's; 0 where that lane is outside the wave).
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp_mov64(int64_t v)
 {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, 0x138, 0xf, 0xf, true);  // wave_shr:1
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)((uint64_t)v >> 32), 0x138, 0xf, 0xf, true);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)((uint64_t)v >> 32), CTRL, 0xf, 0xf, true);
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
@@ -1878,7 +1880,12 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             // inside a run that was).  Lane q works out instruction q's two
             // keys (as the steps do), compares them with lane q - 1's, and
             // the loop visits only the steps left in `todo` (the plain loop
-            // where none is left out).
+            // where none is left out).  A step whose run lies strictly inside
+            // the next instruction's run is left out too: a step left out
+            // leans on a neighbour (back: inside its run; forward: strictly
+            // inside), two neighbours never lean on each other (that would
+            // make their runs equal and unequal), so every chain of leaning
+            // steps ends at a step that runs, and holds its keys.
             uint64_t todo = 0;
             if constexpr (MODE == 3) {
                 const int64_t ubase_last = ubase0 + (int64_t)(__popcll(vmask) - 1) * uelem;
@@ -1886,8 +1893,12 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 const uint32_t kz = (uint32_t)(((uint64_t)ubase_last + ic.SL) >> ll);
                 const uint32_t pf = (uint32_t)__builtin_amdgcn_mov_dpp((int)kf, 0x138, 0xf, 0xf, true);  // wave_shr:1
                 const uint32_t pz = (uint32_t)__builtin_amdgcn_mov_dpp((int)kz, 0x138, 0xf, 0xf, true);
+                const uint32_t nf = (uint32_t)__builtin_amdgcn_mov_dpp((int)kf, 0x130, 0xf, 0xf, true);  // wave_shl:1
+                const uint32_t nz = (uint32_t)__builtin_amdgcn_mov_dpp((int)kz, 0x130, 0xf, 0xf, true);
                 const uint64_t in = n_in >= 64 ? ~0ull : ((1ull << n_in) - 1);
-                const uint64_t same = __ballot(kf >= pf && kz <= pz) & in & ~1ull;
+                const uint64_t back = __ballot(kf >= pf && kz <= pz) & ~1ull;
+                const uint64_t fwd = __ballot(kf >= nf && kz <= nz && (kf != nf || kz != nz)) & (in >> 1);
+                const uint64_t same = (back | fwd) & in;
                 todo = in & ~same;
                 acc_skip += (int64_t)__popcll(same) * __popcll(vmask);
             }
@@ -1905,27 +1916,27 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                 const int64_t a0 = ubase0 + ic.S, a1 = ubase_last + ic.S;
                 const uint32_t lf = (uint32_t)((a0 >> ll) - umin_l + ic.fl - 1);
                 const uint32_t lz = (uint32_t)((a1 >> ll) - umin_l + ic.fl - 1);
-                const uint32_t sf = (uint32_t)((a0 >> ls) - umin_s + ic.fs - 1);
-                const uint32_t sz = (uint32_t)((a1 >> ls) - umin_s + ic.fs - 1);
-                const uint32_t plf = (uint32_t)__builtin_amdgcn_mov_dpp((int)lf, 0x138, 0xf, 0xf, true);  // wave_shr:1
-                const uint32_t plz = (uint32_t)__builtin_amdgcn_mov_dpp((int)lz, 0x138, 0xf, 0xf, true);
-                const uint32_t psf = (uint32_t)__builtin_amdgcn_mov_dpp((int)sf, 0x138, 0xf, 0xf, true);
-                const uint32_t psz = (uint32_t)__builtin_amdgcn_mov_dpp((int)sz, 0x138, 0xf, 0xf, true);
-                const int32_t pst = __builtin_amdgcn_mov_dpp(ic.st, 0x138, 0xf, 0xf, true);
+                // sector runs: in-range keys (mode 2) or sector indices (mode 1)
+                const int64_t sf = MODE == 2 ? (int64_t)(uint32_t)((a0 >> ls) - umin_s + ic.fs - 1) : (a0 >> ls);
+                const int64_t sz = MODE == 2 ? (int64_t)(uint32_t)((a1 >> ls) - umin_s + ic.fs - 1) : (a1 >> ls);
                 const bool lines = PASS == PASS_L || w_lines;
                 const bool secs = PASS == PASS_W || do_sec;
-                bool secs_inside;
-                if constexpr (MODE == 2) {
-                    secs_inside = sf >= psf && sz <= psz;
-                } else {
-                    const int64_t s0 = a0 >> ls, s1 = a1 >> ls;
-                    const int64_t ps0 = dpp_shr64(s0), ps1 = dpp_shr64(s1);
-                    secs_inside = s0 >= ps0 && s1 <= ps1;
-                }
-                const bool inside = (PASS != PASS_W || ic.st == pst) && (!lines || (lf >= plf && lz <= plz)) &&
-                                    (!secs || secs_inside);
+                // this instruction's runs inside instruction (q + d)'s, d = -1, 1
+                auto inside_of = [&](auto ctrl_tag, bool strict) {
+                    constexpr int C = decltype(ctrl_tag)::value;
+                    const uint32_t olf = (uint32_t)__builtin_amdgcn_mov_dpp((int)lf, C, 0xf, 0xf, true);
+                    const uint32_t olz = (uint32_t)__builtin_amdgcn_mov_dpp((int)lz, C, 0xf, 0xf, true);
+                    const int64_t osf = dpp_mov64<C>(sf), osz = dpp_mov64<C>(sz);
+                    const int32_t ost = __builtin_amdgcn_mov_dpp(ic.st, C, 0xf, 0xf, true);
+                    const bool l_in = !lines || (lf >= olf && lz <= olz);
+                    const bool s_in = !secs || (sf >= osf && sz <= osz);
+                    const bool equal = (!lines || (lf == olf && lz == olz)) && (!secs || (sf == osf && sz == osz));
+                    return (PASS != PASS_W || ic.st == ost) && l_in && s_in && !(strict && equal);
+                };
                 const uint64_t in = n_in >= 64 ? ~0ull : ((1ull << n_in) - 1);
-                const uint64_t same = __ballot(inside) & in & ~1ull;
+                const uint64_t back = __ballot(inside_of(std::integral_constant<int, 0x138>{}, false)) & ~1ull;
+                const uint64_t fwd = __ballot(inside_of(std::integral_constant<int, 0x130>{}, true)) & (in >> 1);
+                const uint64_t same = (back | fwd) & in;
                 todo = in & ~same;
                 acc_skip += (int64_t)__popcll(same) * __popcll(vmask);
             }
