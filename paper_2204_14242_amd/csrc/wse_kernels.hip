@@ -1904,8 +1904,9 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
             }
             // The same for steps that set a run of sector keys and a run of
             // line keys (wave pass, and layer steps): a step adds nothing when
-            // both runs, where it sets them, lie inside the previous
-            // instruction's runs and (wave pass) it writes the same kind's
+            // both runs, where it sets them, lie inside a neighbouring
+            // instruction's runs (the previous one's, or strictly inside the
+            // next one's, as above) and (wave pass) it writes the same kind's
             // sector bitmap.  Line keys are in range here, so a line run
             // inside another is of the same field.  Where sectors may leave
             // the table (layer mode 1) the step sets the part of its sector
