@@ -1405,6 +1405,14 @@ __device__ __forceinline__ WordProbe word_probe_runs(const PassCtx& P, uint32_t 
     return word_probe_seg(P, base, act, key, (uint32_t)__builtin_amdgcn_readlane((int)key, first), am);
 }
 
+// word_probe_runs for a mask `am` whose first lane is lane 0 (a row-order
+// segment's valid lanes): the first key is lane 0's, read at a fixed lane.
+__device__ __forceinline__ WordProbe word_probe_lane0(const PassCtx& P, uint32_t base, bool act, uint32_t key,
+                                                      uint64_t am)
+{
+    return word_probe_seg(P, base, act, key, (uint32_t)__builtin_amdgcn_readlane((int)key, 0), am);
+}
+
 // Keeps the compiler from sinking the probes' slot reads into their commits,
 // so that the reads of one step are in flight together.
 __device__ __forceinline__ void probes_issued() { asm volatile("" ::: "memory"); }
@@ -2001,8 +2009,8 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                             if (FAST) {
                                 // every valid key is in range unless the item
                                 // reports an error: the valid lanes give the range
-                                a = word_probe_runs(P, bs + (st ? words_s : 0u), act, ks, vmask);
-                                if (w_lines) b = word_probe_runs(P, bl, act, kl, vmask);
+                                a = word_probe_lane0(P, bs + (st ? words_s : 0u), act, ks, vmask);
+                                if (w_lines) b = word_probe_lane0(P, bl, act, kl, vmask);
                             } else {
                                 a = word_probe(P, bs + (st ? words_s : 0u), act, ks);
                                 if (w_lines) b = word_probe(P, bl, act, kl);
@@ -2041,13 +2049,13 @@ __device__ __forceinline__ void run_pass(PassCtx& P, Counters* ctr, int64_t k_lo
                                                                        ll);
                                     b = word_probe_seg(P, bl, actl, kl, kfirst, vmask);
                                 } else {
-                                    b = word_probe_runs(P, bl, actl, kl, vmask);
+                                    b = word_probe_lane0(P, bl, actl, kl, vmask);
                                 }
                                 if (MODE == 1) {
                                     const uint64_t ams = __ballot(in);
                                     if (ams) a = word_probe_runs(P, bs, in, ks, ams);
                                 } else if (MODE == 2) {
-                                    a = word_probe_runs(P, bs, in, ks, vmask);
+                                    a = word_probe_lane0(P, bs, in, ks, vmask);
                                 }
                             } else {
                                 b = word_probe(P, bl, actl, kl);
