@@ -331,8 +331,9 @@ wse_status wse_get_tuning(wse_ctx* ctx, wse_tuning* tuning);
 wse_status wse_set_tuning(wse_ctx* ctx, const wse_tuning* tuning);
 /* Autotuner: estimate a seeded sample of about `sample` configurations of
  * the given spaces under candidate tunings (coordinate descent over the
- * five parameters), keep the fastest on this device, install it in the
- * context and return it in *chosen. */
+ * five parameters, starting from the context's tuning; a candidate replaces
+ * the incumbent only when it measures at least 3 % faster), install the
+ * result in the context and return it in *chosen. */
 wse_status wse_autotune(wse_ctx* ctx, const wse_space* spaces, int32_t n_spaces, int32_t sample,
                         wse_tuning* chosen);
 

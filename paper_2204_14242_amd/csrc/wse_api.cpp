@@ -1524,6 +1524,9 @@ static wse_status timed_run(wse_ctx* c, const std::vector<wse_space>& spaces, hi
     return s;
 }
 
+// how much faster than the incumbent an autotuner candidate must measure
+constexpr double kAutotuneMargin = 0.03;
+
 extern "C" wse_status wse_autotune(wse_ctx* c, const wse_space* spaces, int32_t n_spaces, int32_t sample,
                                    wse_tuning* chosen)
 {
@@ -1573,7 +1576,10 @@ extern "C" wse_status wse_autotune(wse_ctx* c, const wse_space* spaces, int32_t 
             put_tuning(c, &t);
             double ms = 0;
             wse_status s = timed_run(c, sub, c->rs, &ms);
-            if (s == WSE_OK && ms < best_ms) {
+            // a candidate replaces the incumbent only when it is clearly
+            // faster: the sample's run-to-run spread is a few percent, and a
+            // choice made on noise can cost other spaces much more
+            if (s == WSE_OK && ms < best_ms * (1.0 - kAutotuneMargin)) {
                 best = t;
                 best_ms = ms;
             }
